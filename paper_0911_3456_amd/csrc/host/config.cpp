@@ -1,0 +1,378 @@
+// Kernel configurations: defaults, validation, geometry and source generation.
+//
+// A configuration is the set of code-variant knobs the paper's vision
+// application tunes over (Sec. 6.2: loop unrolling depth, block/grid
+// dimensions, thread work size, shared-memory padding), extended by the
+// matrix-core tiling.  Each knob becomes a -D constant of the kernel source
+// (Sec. 5.3, keyword substitution), so every variant is compiled for exactly
+// one problem (Sec. 4.2).
+#include "geometry.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <sstream>
+
+namespace fbc {
+
+int Config::get(const char* k) const {
+    auto it = v.find(k);
+    return it == v.end() ? 0 : it->second;
+}
+
+std::string Config::str() const {
+    std::string s = "algo=" + algo;
+    for (auto& kv : v) s += " " + kv.first + "=" + std::to_string(kv.second);
+    return s;
+}
+
+bool parse_config(const std::string& text, Config& base, std::string& err) {
+    std::istringstream is(text);
+    std::string tok;
+    Config c = base;
+    while (is >> tok) {
+        auto eq = tok.find('=');
+        if (eq == std::string::npos || eq == 0) { err = "bad token '" + tok + "'"; return false; }
+        std::string k = tok.substr(0, eq), val = tok.substr(eq + 1);
+        if (k == "algo") {
+            if (val != "igemm" && val != "direct" && val != "dw") { err = "unknown algo '" + val + "'"; return false; }
+            if (val != c.algo) {
+                c.algo = val;
+                c.v.clear();          // keys of another algorithm do not carry over
+            }
+            continue;
+        }
+        char* end = nullptr;
+        long x = strtol(val.c_str(), &end, 10);
+        if (!end || *end || val.empty()) { err = "bad value in '" + tok + "'"; return false; }
+        c.v[k] = (int)x;
+    }
+    base = c;
+    return true;
+}
+
+static int round_up(int a, int m) { return (a + m - 1) / m * m; }
+static int cdiv(int a, int b) { return (a + b - 1) / b; }
+static int cdivl(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------ defaults
+
+static int pick_kc(int cin, bool lowp) {
+    if (lowp) {
+        if (cin % 16 == 0) return 16;
+        if (cin % 8 == 0) return 8;
+        return cin <= 16 ? cin : 8;
+    }
+    if (cin <= 16) return cin;
+    if (cin % 16 == 0) return 16;
+    if (cin % 8 == 0) return 8;
+    return 8;
+}
+
+static int pick_shift(int cout) {
+    if (cout >= 32) return 1;
+    if (cout >= 16) return 2;
+    if (cout >= 8) return 4;
+    return 8;
+}
+
+Config default_igemm(int cin, int cout, bool lowp) {
+    Config c;
+    c.algo = "igemm";
+    const int s = pick_shift(cout);
+    const int cols = cout * s;
+    int nt = cols >= 64 ? 2 : 1;
+    c.v = {{"kc", pick_kc(cin, lowp)}, {"s", s}, {"mt", 1}, {"nt", nt}, {"wm", 4}, {"wn", 1},
+           {"xpad", lowp ? 8 : 4}, {"wpad", lowp ? 8 : 4}, {"ustage", 1}, {"xcd", 1}};
+    return c;
+}
+
+Config default_direct(const fbcorr_desc& d) {
+    Config c;
+    c.algo = "direct";
+    int q = 16;
+    while (q > 4 && q > round_up(d.N, 4)) q /= 2;
+    int nb = std::min(64, round_up(d.N, q));
+    c.v = {{"th", 8}, {"tw", 32}, {"p", 4}, {"q", q}, {"nb", nb}, {"ds", 1}, {"layout", 1},
+           {"xpad", 1}, {"wpad", 4}, {"ud", 1}, {"xcd", 1}};
+    // keep the workgroup within 1024 threads
+    while ((c.v["th"] * (c.v["tw"] / c.v["p"]) * (nb / q)) > 1024 && c.v["th"] > 1) c.v["th"] /= 2;
+    return c;
+}
+
+Config default_dw(const fbcorr_desc& d, int cus) {
+    Config c;
+    c.algo = "dw";
+    int wm = d.N <= 32 ? 1 : (d.N <= 64 ? 2 : 4);
+    int wn = std::max(1, 8 / wm);
+    c.v = {{"rh", 4}, {"rw", 32}, {"mt", 1}, {"nt", 3}, {"wm", wm}, {"wn", wn}, {"gpad", 4}, {"xpad", 4}, {"np", 0}};
+    (void)cus;
+    return c;
+}
+
+Config default_config(const fbcorr_desc& d, int role, int cus) {
+    const bool lowp = d.precision != FBCORR_FP32;
+    switch (role) {
+    case FBCORR_ROLE_FORWARD:
+        if (d.algo == FBCORR_ALGO_DIRECT && !lowp) return default_direct(d);
+        return default_igemm(d.D, d.N, lowp);
+    case FBCORR_ROLE_BACKWARD_X:
+        return default_igemm(d.N, d.D, false);
+    default:
+        return default_dw(d, cus);
+    }
+}
+
+// ---------------------------------------------------------- geometry
+
+static void opt(std::vector<std::string>& o, const char* k, long v) {
+    // Every constant is passed as FB_<name>: hiprtc's implicit runtime header
+    // sees -D macros too, and short names such as N would collide with it.
+    o.push_back(std::string("-DFB_") + k + "=" + std::to_string(v));
+}
+
+// igemm: valid correlation over a virtually padded input (see igemm.hip).
+static bool geom_igemm(const Config& c, int batch, int hi, int wi, int cin, int cout, int fh, int fw,
+                       int padh, int padw, int dt, const DeviceInfo& di, LaunchGeom& g,
+                       KernelSource& ks, std::string& err) {
+    const int kc = c.get("kc"), s = c.get("s"), mt = c.get("mt"), nt = c.get("nt");
+    const int wm = c.get("wm"), wn = c.get("wn"), xpad = c.get("xpad"), wpad = c.get("wpad");
+    const int ustage = c.get("ustage"), xcd = c.get("xcd");
+    if (kc < 1 || s < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || xpad < 0 || wpad < 0 || ustage < 1) {
+        err = "igemm: every knob must be positive"; return false;
+    }
+    if (s != 1 && s != 2 && s != 4 && s != 8) { err = "igemm: s must be 1, 2, 4 or 8"; return false; }
+    const int threads = wm * wn * 64;
+    if (threads > std::min(1024, di.max_threads)) { err = "igemm: too many threads"; return false; }
+    if (mt * nt > 8) { err = "igemm: more than 8 accumulator tiles per wave"; return false; }
+    const int ncol = wn * nt * 32;
+    if (ncol % s) { err = "igemm: columns must split evenly into shifts"; return false; }
+    const int cb = ncol / s;
+    const int ho = hi + 2 * padh - fh + 1, wo = wi + 2 * padw - fw + 1;
+    const int esz = dt == 0 ? 4 : 2;
+    const int runit = dt == 0 ? 8 : 16;
+    const int krraw = (fw + s - 1) * kc;
+    const int kr = round_up(krraw, runit);
+    const int rowe = 31 * s * kc + kr;
+    const int rows = rowe + xpad;
+    const int wrs = kr + wpad;
+    int av;
+    if (dt == 0) av = ((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1);
+    else av = ((s * kc) % 8 == 0) ? 8 : (((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1));
+    if (rows % av) { err = "igemm: xpad breaks A-read alignment"; return false; }
+    if (dt == 0 ? (wrs % 4) : (wrs % 8)) { err = "igemm: wpad breaks B-read alignment"; return false; }
+    const int th = wm * mt;
+    const int tr = th + fh - 1;
+    const long lds = (long)(tr * rows + std::min(ustage, fh) * ncol * wrs) * esz;
+    if (lds > di.lds_per_block) { err = "igemm: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
+    const long grid = (long)cdiv(wo, 32 * s) * cdiv(ho, th) * cdiv(cout, cb) * batch;
+    if (grid <= 0 || grid > 0x7fffffffL) { err = "igemm: grid out of range"; return false; }
+    g.grid_x = (int)grid;
+    g.grid_y = 1;
+    g.threads = threads;
+    g.lds = (int)lds;
+    ks.name = "fbcorr_igemm";
+    ks.file = "igemm";
+    ks.source = template_source("igemm");
+    ks.options.clear();
+    opt(ks.options, "BATCH", batch); opt(ks.options, "FH", fh); opt(ks.options, "FW", fw);
+    opt(ks.options, "CIN", cin); opt(ks.options, "COUT", cout);
+    opt(ks.options, "HI", hi); opt(ks.options, "WI", wi); opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
+    opt(ks.options, "PADH", padh); opt(ks.options, "PADW", padw);
+    opt(ks.options, "KC", kc); opt(ks.options, "S", s); opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
+    opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "DT", dt);
+    opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad);
+    opt(ks.options, "USTAGE", std::min(ustage, fh)); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    return true;
+}
+
+static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo& di, LaunchGeom& g,
+                        KernelSource& ks, std::string& err) {
+    const int th = c.get("th"), tw = c.get("tw"), p = c.get("p"), q = c.get("q"), nb = c.get("nb");
+    const int ds = c.get("ds"), layout = c.get("layout"), xpad = c.get("xpad"), wpad = c.get("wpad");
+    const int ud = c.get("ud"), xcd = c.get("xcd");
+    if (th < 1 || tw < 1 || p < 1 || q < 1 || nb < 1 || ds < 1 || xpad < 0 || wpad < 0 || ud < 1) {
+        err = "direct: every knob must be positive"; return false;
+    }
+    if (tw % p) { err = "direct: p must divide tw"; return false; }
+    if (nb % q) { err = "direct: q must divide nb"; return false; }
+    if (q % 4) { err = "direct: q must be a multiple of 4"; return false; }
+    if ((ds & (ds - 1)) || ds > 64 || d.D % ds) { err = "direct: ds must be a power of two dividing D"; return false; }
+    if ((nb + wpad) % 4) { err = "direct: nb + wpad must be a multiple of 4"; return false; }
+    if (layout != 0 && layout != 1) { err = "direct: layout is 0 or 1"; return false; }
+    const int threads = th * (tw / p) * (nb / q) * ds;
+    if (threads > std::min(1024, di.max_threads) || threads < 64 || threads % 64) {
+        err = "direct: workgroup must be 64..1024 threads in whole waves"; return false;
+    }
+    const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
+    const int trr = th + d.fh - 1, tcc = tw + d.fw - 1;
+    const long tile = layout == 0 ? (long)trr * (tcc * d.D + xpad) : (long)d.D * trr * (tcc + xpad);
+    const long lds = (tile + (long)d.fw * d.D * (nb + wpad)) * 4;
+    if (lds > di.lds_per_block) { err = "direct: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
+    const long grid = (long)cdiv(wo, tw) * cdiv(ho, th) * cdiv(d.N, nb) * d.batch;
+    if (grid <= 0 || grid > 0x7fffffffL) { err = "direct: grid out of range"; return false; }
+    g.grid_x = (int)grid;
+    g.grid_y = 1;
+    g.threads = threads;
+    g.lds = (int)lds;
+    ks.name = "fbcorr_direct";
+    ks.file = "direct";
+    ks.source = template_source("direct");
+    ks.options.clear();
+    opt(ks.options, "BATCH", d.batch); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw);
+    opt(ks.options, "D", d.D); opt(ks.options, "N", d.N); opt(ks.options, "H", d.H); opt(ks.options, "W", d.W);
+    opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
+    opt(ks.options, "TH", th); opt(ks.options, "TW", tw); opt(ks.options, "P", p); opt(ks.options, "Q", q);
+    opt(ks.options, "NB", nb); opt(ks.options, "DS", ds); opt(ks.options, "LAYOUT", layout);
+    opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad); opt(ks.options, "UD", ud);
+    opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    return true;
+}
+
+static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di, LaunchGeom& g,
+                    KernelSource& ks, int& np_out, std::string& err) {
+    const int rh = c.get("rh"), rw = c.get("rw"), mt = c.get("mt"), nt = c.get("nt");
+    const int wm = c.get("wm"), wn = c.get("wn"), gpad = c.get("gpad"), xpad = c.get("xpad");
+    int np = c.get("np");
+    if (rh < 1 || rw < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || gpad < 0 || xpad < 0 || np < 0) {
+        err = "dw: every knob must be positive"; return false;
+    }
+    if ((rh * rw) % 2) { err = "dw: rh*rw must be even"; return false; }
+    if (mt * nt > 8) { err = "dw: more than 8 accumulator tiles per wave"; return false; }
+    const int threads = wm * wn * 64;
+    if (threads > std::min(1024, di.max_threads)) { err = "dw: too many threads"; return false; }
+    const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
+    const int qtot = d.fh * d.fw * d.D;
+    const int rb = wm * mt * 32, cbk = wn * nt * 32;
+    const int pc = rh * rw;
+    const long lds = ((long)pc * (rb + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
+    if (lds > di.lds_per_block) { err = "dw: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
+    const long nchunks = (long)d.batch * cdiv(ho, rh) * cdiv(wo, rw);
+    const int gy = cdiv(d.N, rb) * cdiv(qtot, cbk);
+    if (np == 0) {
+        // enough workgroups for about two per compute unit, at most one per chunk
+        long want = cdivl(2L * std::max(di.cus, 1), gy);
+        np = (int)std::min<long>(std::max<long>(want, 1), nchunks);
+    }
+    if (np > nchunks) np = (int)nchunks;
+    if (np < 1 || np > 65535) { err = "dw: partial count out of range"; return false; }
+    g.grid_x = np;
+    g.grid_y = gy;
+    g.threads = threads;
+    g.lds = (int)lds;
+    np_out = np;
+    ks.name = "fbcorr_dw_partial";
+    ks.file = "dw";
+    ks.source = template_source("dw");
+    ks.options.clear();
+    opt(ks.options, "BATCH", d.batch); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw);
+    opt(ks.options, "D", d.D); opt(ks.options, "N", d.N); opt(ks.options, "H", d.H); opt(ks.options, "W", d.W);
+    opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
+    opt(ks.options, "RH", rh); opt(ks.options, "RW", rw); opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
+    opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "GPAD", gpad); opt(ks.options, "XPAD", xpad);
+    return true;
+}
+
+static KernelSource util_source(const char* name, const char* define) {
+    KernelSource ks;
+    ks.name = name;
+    ks.file = "util";
+    ks.source = template_source("util");
+    ks.options.push_back(std::string("-DFB_") + define);
+    return ks;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,
+                            RoleBuild& rb, std::string& err);
+
+bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,
+                RoleBuild& rb, std::string& err) {
+    if (!build_role_impl(d, role, c, di, rb, err)) return false;
+    // Test hook: "inject_error=1" makes the generated source fail to compile.
+    if (c.get("inject_error")) rb.main.options.push_back("-DFB_INJECT_ERROR");
+    return true;
+}
+
+static bool known_keys(const Config& c, std::string& err) {
+    static const std::map<std::string, std::vector<std::string>> keys = {
+        {"igemm", {"kc", "s", "mt", "nt", "wm", "wn", "xpad", "wpad", "ustage", "xcd"}},
+        {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd"}},
+        {"dw", {"rh", "rw", "mt", "nt", "wm", "wn", "gpad", "xpad", "np"}},
+    };
+    auto it = keys.find(c.algo);
+    if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }
+    for (auto& kv : c.v) {
+        if (kv.first == "inject_error") continue;
+        if (std::find(it->second.begin(), it->second.end(), kv.first) == it->second.end()) {
+            err = "unknown key '" + kv.first + "' for algo=" + c.algo;
+            return false;
+        }
+    }
+    return true;
+}
+
+static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,
+                            RoleBuild& rb, std::string& err) {
+    rb = RoleBuild();
+    rb.cfg = c;
+    if (!known_keys(c, err)) return false;
+    const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
+    const long K = (long)d.fh * d.fw * d.D;
+    if (role == FBCORR_ROLE_FORWARD) {
+        const int dt = d.precision == FBCORR_BF16 ? 1 : (d.precision == FBCORR_FP16 ? 2 : 0);
+        if (c.algo == "direct") {
+            if (dt != 0) { err = "the direct kernel is fp32 only"; return false; }
+            if (!geom_direct(c, d, di, rb.main_geom, rb.main, err)) return false;
+        } else if (c.algo == "igemm") {
+            if (!geom_igemm(c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di, rb.main_geom, rb.main, err))
+                return false;
+        } else {
+            err = "forward role needs algo=igemm or algo=direct";
+            return false;
+        }
+        if (dt != 0) {
+            KernelSource ks = util_source("fbcorr_pack_lowp", "PACK_LOWP");
+            opt(ks.options, "N", d.N); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw);
+            opt(ks.options, "D", d.D); opt(ks.options, "LOWP", dt);
+            rb.aux.push_back(ks);
+            rb.aux_geom.push_back(LaunchGeom{d.N, 1, 256, 0});
+            rb.ws_lowp_w = 0;
+            rb.ws_unscale = align256((size_t)d.N * K * 2);
+            rb.ws_bytes = rb.ws_unscale + align256((size_t)d.N * 4);
+        }
+        return true;
+    }
+    if (role == FBCORR_ROLE_BACKWARD_X) {
+        if (c.algo != "igemm") { err = "input-gradient role needs algo=igemm"; return false; }
+        // dx = valid correlation of dy (padded by fh-1, fw-1) with flipped,
+        // transposed filters: CIN = N, COUT = D, input extent Ho x Wo.
+        if (!geom_igemm(c, d.batch, ho, wo, d.N, d.D, d.fh, d.fw, d.fh - 1, d.fw - 1, 0, di,
+                        rb.main_geom, rb.main, err))
+            return false;
+        KernelSource ks = util_source("fbcorr_flip_filters", "FLIP_FILTERS");
+        opt(ks.options, "N", d.N); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw); opt(ks.options, "D", d.D);
+        rb.aux.push_back(ks);
+        rb.aux_geom.push_back(LaunchGeom{cdivl((long)d.N * K, 256), 1, 256, 0});
+        rb.ws_bytes = align256((size_t)d.N * K * 4);
+        return true;
+    }
+    if (role == FBCORR_ROLE_BACKWARD_W) {
+        if (c.algo != "dw") { err = "filter-gradient role needs algo=dw"; return false; }
+        int np = 0;
+        if (!geom_dw(c, d, di, rb.main_geom, rb.main, np, err)) return false;
+        rb.np = np;
+        const long L = (long)d.N * K;
+        const int rs = 4;
+        KernelSource ks = util_source("fbcorr_sum_partials", "SUM_PARTIALS");
+        opt(ks.options, "L", L); opt(ks.options, "NP", np); opt(ks.options, "RS", rs);
+        rb.aux.push_back(ks);
+        rb.aux_geom.push_back(LaunchGeom{cdivl(L, 64), 1, 64 * rs, 0});
+        rb.ws_bytes = align256((size_t)np * L * 4);
+        return true;
+    }
+    err = "unknown role";
+    return false;
+}
+
+}  // namespace fbc

@@ -1,0 +1,37 @@
+// Launch geometry and per-role build descriptions.
+#pragma once
+
+#include "internal.h"
+
+namespace fbc {
+
+struct LaunchGeom {
+    int grid_x = 0, grid_y = 1;
+    int threads = 0;
+    int lds = 0;
+};
+
+// Everything needed to run one role: the main kernel, helper kernels (run
+// before the main kernel for the forward/input-gradient roles, after it for
+// the filter-gradient role), their launch shapes, and workspace use.
+struct RoleBuild {
+    Config cfg;
+    KernelSource main;
+    LaunchGeom main_geom;
+    std::vector<KernelSource> aux;
+    std::vector<LaunchGeom> aux_geom;
+    size_t ws_bytes = 0;
+    size_t ws_lowp_w = 0, ws_unscale = 0;   // forward low-precision layout
+    int np = 0;                             // filter-gradient partial count
+};
+
+Config default_config(const fbcorr_desc& d, int role, int cus);
+Config default_igemm(int cin, int cout, bool lowp);
+Config default_direct(const fbcorr_desc& d);
+bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,
+                RoleBuild& rb, std::string& err);
+
+// Tuning grids (tune.cpp).
+std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_direct);
+
+}  // namespace fbc

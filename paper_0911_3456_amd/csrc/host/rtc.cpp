@@ -1,0 +1,202 @@
+// Run-time code generation core: hiprtc compilation behind an in-process
+// cache, module loading, device facts, errors.
+//
+// The paper's compile path (Sec. 5, Fig. 2): source string -> cache lookup
+// keyed by the source and the hardware/software environment -> compile on a
+// miss -> load -> fetch the function.  Here the key is a hash of the
+// generated source, every compile option, the target architecture and the
+// hiprtc version; the cache lives for the process.
+#include "internal.h"
+
+#include <cstring>
+#include <sstream>
+#include <unordered_map>
+
+#include "kernels_embed.h"   // generated: embedded kernel templates
+
+namespace fbc {
+
+// ---------------------------------------------------------------- errors
+namespace {
+thread_local std::string t_last_error;
+}
+
+void set_error(fbcorr_status s, const std::string& msg) {
+    t_last_error = std::string(fbcorr_status_string(s)) + ": " + msg;
+}
+void clear_error() { t_last_error.clear(); }
+
+// ------------------------------------------------------------ templates
+const std::string& template_source(const std::string& file) {
+    static std::map<std::string, std::string> table = [] {
+        std::map<std::string, std::string> t;
+        for (size_t i = 0; i < kEmbeddedCount; ++i) t[kEmbedded[i].name] = kEmbedded[i].text;
+        return t;
+    }();
+    static const std::string empty;
+    auto it = table.find(file);
+    return it == table.end() ? empty : it->second;
+}
+
+// ---------------------------------------------------------------- hashing
+static uint64_t fnv1a(const std::string& s, uint64_t h = 1469598103934665603ull) {
+    for (unsigned char c : s) { h ^= c; h *= 1099511628211ull; }
+    return h;
+}
+
+std::string hiprtc_version_string() {
+    int major = 0, minor = 0;
+    hiprtcVersion(&major, &minor);
+    return std::to_string(major) + "." + std::to_string(minor);
+}
+
+// ------------------------------------------------------------ compile cache
+namespace {
+std::mutex g_cache_mu;
+std::unordered_map<std::string, std::shared_ptr<const std::vector<char>>> g_code;
+int64_t g_hits = 0, g_misses = 0;
+
+struct LoadedKey {
+    int device;
+    std::string key;
+    bool operator==(const LoadedKey& o) const { return device == o.device && key == o.key; }
+};
+struct LoadedKeyHash {
+    size_t operator()(const LoadedKey& k) const { return std::hash<std::string>()(k.key) ^ (size_t)k.device; }
+};
+std::unordered_map<LoadedKey, hipModule_t, LoadedKeyHash> g_modules;
+}  // namespace
+
+static std::string cache_key(const KernelSource& ks, const std::string& arch) {
+    std::string all = ks.source;
+    all += '\x1f';
+    for (auto& o : ks.options) { all += o; all += '\x1f'; }
+    all += arch;
+    all += '\x1f';
+    all += hiprtc_version_string();
+    char buf[40];
+    snprintf(buf, sizeof buf, "%016llx-%016llx", (unsigned long long)fnv1a(all),
+             (unsigned long long)fnv1a(all, 0x84222325cbf29ce4ull));
+    return ks.name + "-" + buf;
+}
+
+static bool supported_arch(const std::string& a) {
+    // The kernels use CDNA3/CDNA4 matrix instructions; gfx950 is the target.
+    return a == "gfx950";
+}
+
+fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
+                             std::shared_ptr<const std::vector<char>>& code) {
+    FBC_RETURN_IF(!supported_arch(arch), FBCORR_ERR_UNSUPPORTED, "architecture '" + arch + "' is not supported");
+    const std::string key = cache_key(ks, arch);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_code.find(key);
+        if (it != g_code.end()) { ++g_hits; code = it->second; return FBCORR_OK; }
+        ++g_misses;
+    }
+    hiprtcProgram prog;
+    hiprtcResult r = hiprtcCreateProgram(&prog, ks.source.c_str(), (ks.file + ".hip").c_str(), 0, nullptr, nullptr);
+    FBC_RETURN_IF(r != HIPRTC_SUCCESS, FBCORR_ERR_COMPILE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
+    std::vector<std::string> opts;
+    opts.push_back("--offload-arch=" + arch);
+    opts.push_back("-O3");
+    // Packed fp32 instructions are kept out of every kernel.
+    opts.push_back("-Xclang"); opts.push_back("-target-feature");
+    opts.push_back("-Xclang"); opts.push_back("-packed-fp32-ops");
+    for (auto& o : ks.options) opts.push_back(o);
+    std::vector<const char*> cop;
+    for (auto& o : opts) cop.push_back(o.c_str());
+    r = hiprtcCompileProgram(prog, (int)cop.size(), cop.data());
+    if (r != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        std::string optstr;
+        for (auto& o : ks.options) optstr += o + " ";
+        set_error(FBCORR_ERR_COMPILE, ks.name + " [" + optstr + "]: " + log);
+        return FBCORR_ERR_COMPILE;
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    auto buf = std::make_shared<std::vector<char>>(cs);
+    hiprtcGetCode(prog, buf->data());
+    hiprtcDestroyProgram(&prog);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_code[key] = buf;
+    }
+    code = buf;
+    return FBCORR_OK;
+}
+
+void cache_stats(int64_t& hits, int64_t& misses, int64_t& entries) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    hits = g_hits; misses = g_misses; entries = (int64_t)g_code.size();
+}
+
+fbcorr_status device_info(int device, DeviceInfo& out) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    FBC_RETURN_IF(e != hipSuccess || count <= 0, FBCORR_ERR_NO_DEVICE, "no HIP device available");
+    FBC_RETURN_IF(device < 0 || device >= count, FBCORR_ERR_NO_DEVICE,
+                  "device index " + std::to_string(device) + " out of range");
+    hipDeviceProp_t p;
+    e = hipGetDeviceProperties(&p, device);
+    FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_NO_DEVICE, std::string("hipGetDeviceProperties: ") + hipGetErrorString(e));
+    std::string arch = p.gcnArchName;
+    auto colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    out.arch = arch;
+    out.cus = p.multiProcessorCount;
+    out.lds_per_block = (int)p.sharedMemPerBlock;
+    out.max_threads = p.maxThreadsPerBlock;
+    return FBCORR_OK;
+}
+
+fbcorr_status load_kernel(const KernelSource& ks, int device, Kernel& out) {
+    DeviceInfo di;
+    fbcorr_status st = device_info(device, di);
+    if (st != FBCORR_OK) return st;
+    const std::string key = cache_key(ks, di.arch);
+    hipModule_t mod = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_modules.find(LoadedKey{device, key});
+        if (it != g_modules.end()) mod = it->second;
+    }
+    if (!mod) {
+        std::shared_ptr<const std::vector<char>> code;
+        st = compile_cached(ks, di.arch, code);
+        if (st != FBCORR_OK) return st;
+        int prev = 0;
+        hipGetDevice(&prev);
+        hipSetDevice(device);
+        hipError_t e = hipModuleLoadData(&mod, code->data());
+        hipSetDevice(prev);
+        FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto ins = g_modules.emplace(LoadedKey{device, key}, mod);
+        if (!ins.second) {               // another thread won the race
+            hipModuleUnload(mod);
+            mod = ins.first->second;
+        }
+    }
+    hipFunction_t fn = nullptr;
+    hipError_t e = hipModuleGetFunction(&fn, mod, ks.name.c_str());
+    FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("hipModuleGetFunction(") + ks.name + "): " + hipGetErrorString(e));
+    int regs = 0, lds = 0;
+    hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, fn);
+    hipFuncGetAttribute(&lds, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, fn);
+    out.fn = fn;
+    out.vgprs = regs;
+    out.lds_bytes = lds;
+    out.key = key;
+    return FBCORR_OK;
+}
+
+}  // namespace fbc
+
+extern "C" const char* fbcorr_last_error(void) { return fbc::t_last_error.c_str(); }

@@ -1,0 +1,348 @@
+// Automated tuning (Sec. 4.1; Sec. 6.2's "coarse grid search" over code
+// variants).  Variants are generated from a grid of knobs, pruned by
+// resources before anything runs (Sec. 6.1's early rejection of poor
+// variants), compiled in parallel, gated for exactness against the default
+// variant on integer-valued data, timed with HIP events, and the fastest is
+// installed in the plan.
+#include "plan.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <set>
+#include <thread>
+
+namespace fbc {
+
+static int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct TuneLayout {
+    size_t xi = 0, wi = 0, gi = 0, ref = 0, cand = 0, role_ws = 0, total = 0;
+    size_t nx = 0, nw = 0, ny = 0, nout = 0;
+};
+
+static const size_t kMaxPartialsForTuning = 1024;
+
+static TuneLayout tune_layout(const Plan* p) {
+    const fbcorr_desc& d = p->desc;
+    TuneLayout t;
+    t.nx = (size_t)d.batch * d.H * d.W * d.D;
+    t.nw = (size_t)d.N * d.fh * d.fw * d.D;
+    t.ny = (size_t)d.batch * (d.H - d.fh + 1) * (d.W - d.fw + 1) * d.N;
+    t.nout = std::max(t.nx, std::max(t.nw, t.ny));
+    size_t off = 0;
+    t.xi = off; off += align256(t.nx * 4);
+    t.wi = off; off += align256(t.nw * 4);
+    t.gi = off; off += align256(t.ny * 4);
+    t.ref = off; off += align256(t.nout * 4);
+    t.cand = off; off += align256(t.nout * 4);
+    t.role_ws = off;
+    // largest role workspace any candidate may ask for
+    size_t rw = std::max(align256(t.nw * 2) + align256((size_t)d.N * 4), align256(t.nw * 4));
+    rw = std::max(rw, align256(kMaxPartialsForTuning * t.nw * 4));
+    off += rw;
+    t.total = off;
+    return t;
+}
+
+size_t tune_workspace(Plan* p) { return tune_layout(p).total; }
+
+// ------------------------------------------------------------ candidate grids
+
+static void add(std::vector<Config>& out, std::set<std::string>& seen, const Config& c) {
+    if (seen.insert(c.str()).second) out.push_back(c);
+}
+
+std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_direct) {
+    std::vector<Config> out;
+    std::set<std::string> seen;
+    const bool lowp = d.precision != FBCORR_FP32;
+    if (role == FBCORR_ROLE_FORWARD || role == FBCORR_ROLE_BACKWARD_X) {
+        const int cin = role == FBCORR_ROLE_FORWARD ? d.D : d.N;
+        const int cout = role == FBCORR_ROLE_FORWARD ? d.N : d.D;
+        const Config base = default_igemm(cin, cout, lowp && role == FBCORR_ROLE_FORWARD);
+        const bool lp = lowp && role == FBCORR_ROLE_FORWARD;
+        std::vector<int> kcs = {base.get("kc")};
+        for (int kc : {4, 8, 16, 32})
+            if (kc <= cin && cin % kc == 0 && (!lp || kc % 8 == 0)) kcs.push_back(kc);
+        std::vector<int> ss = {base.get("s")};
+        if (base.get("s") > 1) ss.push_back(base.get("s") / 2);
+        // (mt, nt, wm, wn): per-wave tiles and waves per workgroup
+        const int shapes[][4] = {{1, 1, 4, 1}, {1, 2, 4, 1}, {2, 1, 2, 2}, {2, 2, 2, 1}, {1, 2, 2, 2},
+                                 {2, 2, 4, 1}, {1, 4, 4, 1}, {2, 2, 2, 2}, {4, 2, 1, 1}, {1, 1, 8, 1}};
+        for (int kc : kcs)
+            for (int s : ss)
+                for (auto& sh : shapes)
+                    for (int us : {1, 3})
+                        for (int pad : {0, 1}) {
+                            Config c = base;
+                            c.v["kc"] = kc;
+                            c.v["s"] = s;
+                            c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
+                            // skip tiles whose columns exceed what the channels can fill
+                            if (sh[1] * sh[3] * 32 > std::max(32, ((cout * s + 31) / 32) * 32)) continue;
+                            c.v["ustage"] = us;
+                            const int unit = lp ? 8 : 4;
+                            c.v["xpad"] = pad * unit;
+                            c.v["wpad"] = pad * unit;
+                            add(out, seen, c);
+                        }
+        if (with_direct && role == FBCORR_ROLE_FORWARD && !lowp) {
+            const Config db = default_direct(d);
+            for (int th : {4, 8, 16})
+                for (int tw : {16, 32, 64})
+                    for (int p : {2, 4, 8})
+                        for (int q : {8, 16})
+                            for (int nb : {32, 64})
+                                for (int layout : {0, 1}) {
+                                    Config c = db;
+                                    c.v["th"] = th; c.v["tw"] = tw; c.v["p"] = p; c.v["q"] = q;
+                                    c.v["nb"] = std::min(nb, ((d.N + q - 1) / q) * q);
+                                    c.v["layout"] = layout;
+                                    const int thr = th * (tw / p) * (c.v["nb"] / q);
+                                    if (thr < 64 || thr > 1024 || thr % 64) continue;
+                                    add(out, seen, c);
+                                }
+        }
+    } else {
+        const Config base = default_config(d, role, 256);
+        const int shapes[][4] = {{1, 3, 2, 4}, {1, 2, 2, 4}, {2, 3, 1, 4}, {1, 4, 2, 2}, {2, 2, 1, 8},
+                                 {1, 3, 2, 2}, {2, 4, 1, 4}, {1, 1, 2, 8}};
+        for (auto& sh : shapes)
+            for (int rh : {2, 4, 8})
+                for (int np : {0, 128, 256, 512}) {
+                    Config c = base;
+                    c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
+                    if (sh[0] * sh[2] * 32 > std::max(32, ((d.N + 31) / 32) * 32)) continue;
+                    c.v["rh"] = rh;
+                    c.v["np"] = np;
+                    add(out, seen, c);
+                }
+    }
+    return out;
+}
+
+// ------------------------------------------------------------ running
+
+struct TuneBuffers {
+    const float *x, *w, *g;     // inputs for the role
+    float* out;
+    void* ws;
+};
+
+static fbcorr_status run_role(Plan* p, int role, const RoleExec& ex, const TuneBuffers& b, hipStream_t s) {
+    if (role == FBCORR_ROLE_FORWARD) return run_forward(p, ex, b.x, b.w, b.out, b.ws, s);
+    if (role == FBCORR_ROLE_BACKWARD_X) return run_backward_x(p, ex, b.w, b.g, b.out, b.ws, s);
+    return run_backward_w(p, ex, b.x, b.g, b.out, b.ws, s);
+}
+
+static size_t out_elems(const TuneLayout& t, int role) {
+    return role == FBCORR_ROLE_FORWARD ? t.ny : (role == FBCORR_ROLE_BACKWARD_X ? t.nx : t.nw);
+}
+
+static fbcorr_status fill_int(Plan* p, float* dst, size_t n, unsigned seed, int R, hipStream_t s) {
+    KernelSource ks;
+    ks.name = "fbcorr_fill_int";
+    ks.file = "util";
+    ks.source = template_source("util");
+    ks.options.push_back("-DFB_FILL_INT");
+    Kernel k;
+    fbcorr_status st = load_kernel(ks, p->device, k);
+    if (st != FBCORR_OK) return st;
+    long nn = (long)n;
+    void* args[] = {&dst, &nn, &seed, &R};
+    LaunchGeom g{cdiv(nn, 256), 1, 256, 0};
+    return launch(k, g, s, args);
+}
+
+static fbcorr_status time_role(Plan* p, int role, const RoleExec& ex, const TuneBuffers& b, hipStream_t s,
+                               int warmup, int reps, double& ms) {
+    const bool was = p->timing;
+    p->timing = false;
+    fbcorr_status st = FBCORR_OK;
+    for (int i = 0; i < warmup && st == FBCORR_OK; ++i) st = run_role(p, role, ex, b, s);
+    std::vector<hipEvent_t> ev(reps + 1);
+    for (auto& e : ev) hipEventCreate(&e);
+    hipEventRecord(ev[0], s);
+    for (int i = 0; i < reps && st == FBCORR_OK; ++i) {
+        st = run_role(p, role, ex, b, s);
+        hipEventRecord(ev[i + 1], s);
+    }
+    hipError_t he = hipStreamSynchronize(s);
+    std::vector<double> t;
+    for (int i = 0; i < reps && st == FBCORR_OK; ++i) {
+        float f = 0;
+        hipEventElapsedTime(&f, ev[i], ev[i + 1]);
+        t.push_back(f);
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    p->timing = was;
+    if (st != FBCORR_OK) return st;
+    FBC_RETURN_IF(he != hipSuccess, FBCORR_ERR_LAUNCH, std::string("stream: ") + hipGetErrorString(he));
+    std::sort(t.begin(), t.end());
+    ms = t.empty() ? 1e30 : t[t.size() / 2];
+    return FBCORR_OK;
+}
+
+static fbcorr_status make_exec(Plan* p, int role, const RoleBuild& rb, RoleExec& ex) {
+    ex = RoleExec();
+    ex.build = rb;
+    fbcorr_status st = load_kernel(rb.main, p->device, ex.main);
+    if (st != FBCORR_OK) return st;
+    for (auto& a : rb.aux) {
+        Kernel k;
+        st = load_kernel(a, p->device, k);
+        if (st != FBCORR_OK) return st;
+        ex.aux.push_back(k);
+    }
+    return FBCORR_OK;
+}
+
+}  // namespace fbc
+
+using namespace fbc;
+
+extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const float* w, float* y, void* workspace,
+                                     size_t workspace_bytes, void* stream, const fbcorr_tune_opts* opts,
+                                     fbcorr_tune_report* report) {
+    try {
+        clear_error();
+        Plan* p = reinterpret_cast<Plan*>(plan);
+        FBC_RETURN_IF(!p, FBCORR_ERR_INVALID_ARGUMENT, "plan is NULL");
+        FBC_RETURN_IF(p->batched, FBCORR_ERR_UNSUPPORTED, "batched plans are tuned per key at plan time");
+        const int role = opts ? opts->role : FBCORR_ROLE_FORWARD;
+        FBC_RETURN_IF(role < 0 || role >= FBCORR_ROLE_COUNT, FBCORR_ERR_INVALID_ARGUMENT, "unknown role");
+        const int warmup = (opts && opts->warmup > 0) ? opts->warmup : 2;
+        const int reps = (opts && opts->reps > 0) ? opts->reps : 10;
+        const int maxc = (opts && opts->max_candidates > 0) ? opts->max_candidates : 1 << 30;
+        const bool with_direct = opts && (opts->flags & 1u);
+        fbcorr_status st;
+        if ((st = check_ptr(y, "y"))) return st;
+        if (role != FBCORR_ROLE_BACKWARD_X && (st = check_ptr(x, "x"))) return st;
+        if (role != FBCORR_ROLE_BACKWARD_W && (st = check_ptr(w, "w"))) return st;
+        DeviceGuard guard(p->device);
+        const TuneLayout t = tune_layout(p);
+        if ((st = check_ws(workspace, workspace_bytes, t.total))) return st;
+        hipStream_t s = (hipStream_t)stream;
+        char* base = (char*)workspace;
+        const fbcorr_desc& d = p->desc;
+
+        // Integer-valued gate data: every partial sum stays exact in fp32.
+        long kdepth = role == FBCORR_ROLE_FORWARD ? (long)d.fh * d.fw * d.D
+                      : role == FBCORR_ROLE_BACKWARD_X ? (long)d.fh * d.fw * d.N
+                                                       : (long)d.batch * (d.H - d.fh + 1) * (d.W - d.fw + 1);
+        int R = (int)std::floor(std::sqrt((double)(1 << 24) / (double)kdepth));
+        R = std::max(1, std::min(8, R));
+        const bool exact = (double)R * R * kdepth < (double)(1 << 24);
+        float* xi = (float*)(base + t.xi);
+        float* wi = (float*)(base + t.wi);
+        float* gi = (float*)(base + t.gi);
+        float* ref = (float*)(base + t.ref);
+        float* cand = (float*)(base + t.cand);
+        void* rws = base + t.role_ws;
+        if ((st = fill_int(p, xi, t.nx, 11u, R, s)) || (st = fill_int(p, wi, t.nw, 23u, R, s)) ||
+            (st = fill_int(p, gi, t.ny, 37u, R, s)))
+            return st;
+        const TuneBuffers gate{xi, wi, gi, nullptr, rws};
+        const TuneBuffers timed{x, w, y, nullptr, rws};
+        const size_t nout = out_elems(t, role);
+
+        fbcorr_tune_report rep;
+        memset(&rep, 0, sizeof rep);
+
+        // Default variant: the reference for the gate and the "default" time.
+        const Config dcfg = default_config(d, role, p->dev.cus);
+        RoleBuild drb;
+        std::string err;
+        FBC_RETURN_IF(!build_role(d, role, dcfg, p->dev, drb, err), FBCORR_ERR_UNSUPPORTED, "default: " + err);
+        RoleExec dex;
+        if ((st = make_exec(p, role, drb, dex))) return st;
+        TuneBuffers g1 = gate;
+        g1.out = ref;
+        if ((st = run_role(p, role, dex, g1, s))) return st;
+        std::vector<float> href(nout), hc(nout);
+        hipError_t he = hipMemcpyDtoHAsync(href.data(), (hipDeviceptr_t)ref, nout * 4, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);
+        FBC_RETURN_IF(he != hipSuccess, FBCORR_ERR_LAUNCH, std::string("gate copy: ") + hipGetErrorString(he));
+        float refmax = 0.f;
+        for (float v : href) refmax = std::max(refmax, std::fabs(v));
+        TuneBuffers t1 = timed;
+        t1.out = role == FBCORR_ROLE_FORWARD ? y : cand;
+        double dms = 0;
+        if ((st = time_role(p, role, dex, t1, s, warmup, reps, dms))) return st;
+        rep.default_ms = dms;
+        snprintf(rep.default_cfg, sizeof rep.default_cfg, "%s", dcfg.str().c_str());
+
+        // Candidates: resource pruning, then parallel compilation.
+        std::vector<Config> cands = tune_candidates(d, role, with_direct);
+        std::vector<RoleBuild> builds;
+        for (auto& c : cands) {
+            if ((int)builds.size() >= maxc) break;
+            RoleBuild rb;
+            rep.n_tried++;
+            if (!build_role(d, role, c, p->dev, rb, err)) { rep.n_rejected_resources++; continue; }
+            if (rb.ws_bytes > workspace_bytes - t.role_ws) { rep.n_rejected_resources++; continue; }
+            builds.push_back(rb);
+        }
+        std::vector<int> ok(builds.size(), 0);
+        {
+            std::atomic<size_t> next{0};
+            unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+            std::vector<std::thread> pool;
+            for (unsigned i = 0; i < nth; ++i)
+                pool.emplace_back([&] {
+                    for (size_t j; (j = next++) < builds.size();) {
+                        std::shared_ptr<const std::vector<char>> code;
+                        bool good = compile_cached(builds[j].main, p->dev.arch, code) == FBCORR_OK;
+                        for (auto& a : builds[j].aux)
+                            good = good && compile_cached(a, p->dev.arch, code) == FBCORR_OK;
+                        ok[j] = good ? 1 : 0;
+                    }
+                });
+            for (auto& th : pool) th.join();
+        }
+        double best = dms;
+        int best_i = -1;
+        for (size_t j = 0; j < builds.size(); ++j) {
+            if (!ok[j]) { rep.n_failed++; continue; }
+            rep.n_compiled++;
+            RoleExec ex;
+            if (make_exec(p, role, builds[j], ex) != FBCORR_OK) { rep.n_failed++; continue; }
+            if (ex.main.lds_bytes > p->dev.lds_per_block) { rep.n_rejected_resources++; continue; }
+            TuneBuffers g2 = gate;
+            g2.out = cand;
+            if (run_role(p, role, ex, g2, s) != FBCORR_OK) { rep.n_failed++; continue; }
+            he = hipMemcpyDtoHAsync(hc.data(), (hipDeviceptr_t)cand, nout * 4, s);
+            if (he == hipSuccess) he = hipStreamSynchronize(s);
+            FBC_RETURN_IF(he != hipSuccess, FBCORR_ERR_LAUNCH, std::string("gate copy: ") + hipGetErrorString(he));
+            bool same;
+            if (exact) {
+                same = memcmp(hc.data(), href.data(), nout * 4) == 0;
+            } else {
+                same = true;
+                for (size_t i = 0; i < nout && same; ++i) same = std::fabs(hc[i] - href[i]) <= 1e-5f * refmax;
+            }
+            if (!same) { rep.n_rejected_parity++; continue; }
+            TuneBuffers t2 = timed;
+            t2.out = role == FBCORR_ROLE_FORWARD ? y : cand;
+            double ms = 0;
+            if (time_role(p, role, ex, t2, s, warmup, reps, ms) != FBCORR_OK) { rep.n_failed++; continue; }
+            if (ms < best) { best = ms; best_i = (int)j; }
+        }
+        const Config& chosen = best_i >= 0 ? builds[best_i].cfg : dcfg;
+        rep.best_ms = best;
+        snprintf(rep.best_cfg, sizeof rep.best_cfg, "%s", chosen.str().c_str());
+        st = compile_role(p, role, chosen);
+        if (st != FBCORR_OK) return st;
+        if (report) *report = rep;
+        return FBCORR_OK;
+    } catch (const std::exception& e) {
+        set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what());
+        return FBCORR_ERR_INTERNAL;
+    } catch (...) {
+        set_error(FBCORR_ERR_INTERNAL, "unknown exception");
+        return FBCORR_ERR_INTERNAL;
+    }
+}

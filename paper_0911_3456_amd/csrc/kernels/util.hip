@@ -1,0 +1,132 @@
+// Small helper kernels of the filter-bank correlation library.
+//
+//   fbcorr_sum_partials  out[i] = sum_{p<NP} part[p*L + i]; slice k < RS adds
+//                        p = k, k+RS, k+2RS, ... in increasing order, then the
+//                        RS slice sums are added in increasing k (a fixed
+//                        order, so the result is deterministic).
+//   fbcorr_flip_filters  wf[d,u,v,n] = w[n, FH-1-u, FW-1-v, d]: the filters of
+//                        the input-gradient correlation.
+//   fbcorr_pack_lowp     per filter n: e_n = floor(log2 max|w[n]|),
+//                        wq[n,k] = round_to_nearest_even(w[n,k] * 2^-e_n) as
+//                        bf16 (LOWP=1) or fp16 (LOWP=2), unscale[n] = 2^e_n
+//                        (an all-zero filter gets e_n = 0).
+//   fbcorr_fill_int      integer-valued pattern in [-R, R] (tuner gate data).
+//
+// Compile-time constants: L NP RS (sum); N FH FW D (flip, pack); LOWP (pack).
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#endif
+
+// Specialisation constants arrive as FB_<name> (see the host generator).
+#ifdef FB_L
+#define L FB_L
+#endif
+#ifdef FB_NP
+#define NP FB_NP
+#endif
+#ifdef FB_RS
+#define RS FB_RS
+#endif
+#ifdef FB_N
+#define N FB_N
+#endif
+#ifdef FB_FH
+#define FH FB_FH
+#endif
+#ifdef FB_FW
+#define FW FB_FW
+#endif
+#ifdef FB_D
+#define D FB_D
+#endif
+#ifdef FB_LOWP
+#define LOWP FB_LOWP
+#endif
+
+#ifdef FB_SUM_PARTIALS
+extern "C" __global__ void __launch_bounds__(64 * RS)
+fbcorr_sum_partials(const float* __restrict__ part, float* __restrict__ out)
+{
+    __shared__ float red[RS][64];
+    const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const long i = (long)blockIdx.x * 64 + e;
+    float s = 0.f;
+    if (i < L) {
+        for (int p = sl; p < NP; p += RS) s += part[(long)p * L + i];
+    }
+    red[sl][e] = s;
+    __syncthreads();
+    if (sl == 0 && i < L) {
+        float t = red[0][e];
+#pragma unroll
+        for (int k = 1; k < RS; ++k) t += red[k][e];
+        out[i] = t;
+    }
+}
+#endif
+
+#ifdef FB_FLIP_FILTERS
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_flip_filters(const float* __restrict__ w, float* __restrict__ wf)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)N * FH * FW * D) return;
+    // e indexes wf[d][u][v][n]
+    const int n = e % N;
+    const int v = (e / N) % FW;
+    const int u = (e / ((long)N * FW)) % FH;
+    const int d = e / ((long)N * FW * FH);
+    wf[e] = w[(((long)n * FH + (FH - 1 - u)) * FW + (FW - 1 - v)) * D + d];
+}
+#endif
+
+#ifdef FB_PACK_LOWP
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_pack_lowp(const float* __restrict__ w, unsigned short* __restrict__ wq,
+                 float* __restrict__ unscale)
+{
+    __shared__ float red[256];
+    const int n = blockIdx.x;
+    const int K = FH * FW * D;
+    const float* wn = w + (long)n * K;
+    float m = 0.f;
+    for (int k = threadIdx.x; k < K; k += 256) m = fmaxf(m, fabsf(wn[k]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    m = red[0];
+    int ex = 0;
+    if (m > 0.f) {
+        (void)frexpf(m, &ex);   // m = f * 2^ex, f in [0.5, 1)
+        ex -= 1;                // floor(log2 m)
+    }
+    const float sc = ldexpf(1.0f, -ex);
+    for (int k = threadIdx.x; k < K; k += 256) {
+        const float v = wn[k] * sc;   // exact: power-of-two scale
+#if LOWP == 1
+        const __bf16 hv = (__bf16)v;
+#else
+        const _Float16 hv = (_Float16)v;
+#endif
+        wq[(long)n * K + k] = __builtin_bit_cast(unsigned short, hv);
+    }
+    if (threadIdx.x == 0) unscale[n] = ldexpf(1.0f, ex);
+}
+#endif
+
+#ifdef FB_FILL_INT
+// Integer-valued test pattern in [-R, R] for the tuner's exactness gate:
+// out[i] = (h(i, seed) mod (2R+1)) - R with a 32-bit integer mixing hash.
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_fill_int(float* __restrict__ out, long n, unsigned seed, int R)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    unsigned hsh = (unsigned)i * 0x9E3779B1u ^ (unsigned)(i >> 32) ^ seed;
+    hsh ^= hsh >> 15; hsh *= 0x85EBCA77u; hsh ^= hsh >> 13; hsh *= 0xC2B2AE3Du; hsh ^= hsh >> 16;
+    out[i] = (float)((int)(hsh % (unsigned)(2 * R + 1)) - R);
+}
+#endif

@@ -1,0 +1,145 @@
+"""Host-side tests of the C-ABI library (no GPU needed).
+
+The library loads, exports every entry point include/fbcorr.h declares,
+generates deterministic specialised sources, compiles every role for gfx950
+with hiprtc without a device, and turns bad input into status codes.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_0911_3456_amd import _native
+    return _native, _native.load()
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "fbcorr.h")).read()
+    return sorted(set(re.findall(r"FBCORR_API\s+[\w\s\*]+?\b(fbcorr_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    nat, lib = _lib()
+    syms = _header_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(nat.EXPORTS) == syms
+
+
+def test_status_strings_and_version():
+    nat, lib = _lib()
+    for code, name in nat.STATUS_NAMES.items():
+        assert lib.fbcorr_status_string(code).decode() == name
+    assert lib.fbcorr_version() >= 100
+
+
+def test_codegen_is_deterministic_and_specialised():
+    from paper_0911_3456_amd import codegen, make_desc
+    d = make_desc(1, 256, 256, 8, 64, 9, 9)
+    s1, o1 = codegen(d)
+    s2, o2 = codegen(d)
+    assert s1 == s2 and o1 == o2
+    assert "-DFB_FH=9" in o1 and "-DFB_CIN=8" in o1 and "-DFB_COUT=64" in o1
+    _, o3 = codegen(make_desc(1, 256, 256, 8, 64, 7, 7))
+    assert o3 != o1 and "-DFB_FH=7" in o3
+    _, od = codegen(d, "forward", "algo=direct th=4")
+    assert "-DFB_TH=4" in od
+    _, ob = codegen(d, "backward_x")
+    assert "-DFB_PADH=8" in ob and "-DFB_CIN=64" in ob and "-DFB_COUT=8" in ob
+
+
+@pytest.mark.parametrize("shape,prec", [
+    ((1, 64, 64, 4, 16, 5, 5), "fp32"),
+    ((1, 256, 256, 8, 64, 9, 9), "fp32"),
+    ((1, 512, 512, 16, 128, 13, 13), "bf16"),
+    ((1, 512, 512, 16, 128, 13, 13), "fp16"),
+    ((32, 128, 128, 16, 64, 7, 7), "fp32"),
+    ((2, 37, 45, 3, 7, 3, 4), "fp32"),
+])
+def test_compile_every_role_for_gfx950(shape, prec):
+    from paper_0911_3456_amd import compile_check, make_desc
+    d = make_desc(*shape, precision=prec)
+    assert compile_check(d, "forward") > 0
+    if prec == "fp32":
+        assert compile_check(d, "forward", "algo=direct") > 0
+        assert compile_check(d, "backward_x") > 0
+        assert compile_check(d, "backward_w") > 0
+
+
+def test_compile_cache_hits():
+    from paper_0911_3456_amd import cache_stats, compile_check, make_desc
+    d = make_desc(1, 30, 31, 4, 8, 3, 3)
+    compile_check(d)
+    before = cache_stats()
+    compile_check(d)
+    after = cache_stats()
+    assert after["hits"] > before["hits"]
+    assert after["entries"] == before["entries"]
+
+
+def test_invalid_descriptors_map_to_status():
+    from paper_0911_3456_amd import FbcorrError, codegen, make_desc
+    with pytest.raises(FbcorrError) as e:
+        codegen(make_desc(1, 8, 8, 4, 4, 9, 3))
+    assert e.value.status_name == "FBCORR_ERR_SHAPE"
+    with pytest.raises(FbcorrError) as e:
+        codegen(make_desc(1, 0, 8, 4, 4, 3, 3))
+    assert e.value.status_name == "FBCORR_ERR_INVALID_ARGUMENT"
+    with pytest.raises(FbcorrError) as e:
+        codegen(make_desc(1, 8, 8, 4, 4, 3, 3, precision="bf16", algo="direct"))
+    assert e.value.status_name == "FBCORR_ERR_UNSUPPORTED"
+
+
+def test_bad_configs_rejected_before_compiling():
+    from paper_0911_3456_amd import FbcorrError, codegen, make_desc
+    d = make_desc(1, 256, 256, 8, 64, 9, 9)
+    for cfg in ["algo=igemm s=3", "algo=igemm wm=32", "algo=direct p=3", "algo=igemm kc=8 xpad=1",
+                "algo=igemm mt=4 nt=4", "bogus", "algo=nope", "algo=igemm mtt=2"]:
+        with pytest.raises(FbcorrError):
+            codegen(d, "forward", cfg)
+    with pytest.raises(FbcorrError) as e:
+        codegen(make_desc(1, 256, 256, 64, 128, 13, 13), "forward", "algo=igemm kc=64 ustage=13 nt=4")
+    assert e.value.status_name == "FBCORR_ERR_UNSUPPORTED"    # LDS over the device limit
+
+
+def test_compile_error_is_reported():
+    """An injected code-generation failure comes back as FBCORR_ERR_COMPILE
+    with the compiler log, and the library stays usable."""
+    nat, lib = _lib()
+    d = nat.make_desc(1, 16, 16, 4, 4, 3, 3)
+    n = ctypes.c_size_t(0)
+    for role in (0, 1, 2):
+        st = lib.fbcorr_compile_check(ctypes.byref(d), role, b"inject_error=1", b"gfx950", ctypes.byref(n))
+        assert nat.STATUS_NAMES[st] == "FBCORR_ERR_COMPILE"
+        assert b"injected code-generation failure" in lib.fbcorr_last_error()
+    assert lib.fbcorr_compile_check(ctypes.byref(d), 0, None, b"gfx950", ctypes.byref(n)) == 0
+    st = lib.fbcorr_compile_check(ctypes.byref(d), 0, None, b"gfx_not_a_gpu", ctypes.byref(n))
+    assert nat.STATUS_NAMES[st] == "FBCORR_ERR_UNSUPPORTED"
+
+
+def test_null_arguments():
+    nat, lib = _lib()
+    assert nat.STATUS_NAMES[lib.fbcorr_plan(None, 0, None)] == "FBCORR_ERR_INVALID_ARGUMENT"
+    assert lib.fbcorr_plan_destroy(None) == 0
+    n = ctypes.c_size_t(0)
+    assert nat.STATUS_NAMES[lib.fbcorr_workspace_size(None, 0, ctypes.byref(n))] == "FBCORR_ERR_INVALID_ARGUMENT"
+    assert nat.STATUS_NAMES[lib.fbcorr_forward(None, None, None, None, None, 0, None)] == \
+        "FBCORR_ERR_INVALID_ARGUMENT"
+
+
+def test_plan_without_device_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    nat, lib = _lib()
+    d = nat.make_desc(1, 16, 16, 4, 4, 3, 3)
+    h = ctypes.c_void_p()
+    st = lib.fbcorr_plan(ctypes.byref(d), 0, ctypes.byref(h))
+    assert nat.STATUS_NAMES[st] == "FBCORR_ERR_NO_DEVICE"
+    assert not h.value
