@@ -1,0 +1,219 @@
+"""GPU parity of the gradient kernels (dX, dW) and the autograd wrapper.
+
+The oracle's gradient is the scatter-form adjoint in FP64; the bar is the
+same normalised error as the forward (A = sum|dy||w| for dX, sum|dy||x| for
+dW), and bit-for-bit equality on integer data with exact partial sums.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from _gpu_util import host, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _plan(s, **kw):
+    from paper_0911_3456_amd import Plan
+    return Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, **kw)
+
+
+def _grads(plan, x, w, g, need_dx=True, need_dw=True):
+    xt, wt, gt = to_dev(x, w, g)
+    dx, dw = plan.backward(xt, wt, gt, need_dx=need_dx, need_dw=need_dw)
+    return (host(dx) if dx is not None else None), (host(dw) if dw is not None else None)
+
+
+SHAPES = [
+    (1, 64, 64, 4, 16, 5, 5),
+    (2, 37, 45, 3, 7, 3, 4),
+    (1, 40, 70, 8, 64, 9, 9),
+    (3, 20, 21, 1, 1, 1, 1),
+    (1, 9, 11, 5, 33, 9, 11),
+    (2, 30, 34, 16, 64, 7, 7),
+    (1, 24, 100, 2, 5, 8, 8),
+    (1, 26, 29, 32, 128, 3, 3),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_fp32(shape):
+    need_gpu()
+    s = wl.Shape(*shape)
+    x, w, rng = wl.draw_single(s, seed=300 + sum(shape))
+    g = wl.draw_grad(s, rng)
+    dx, dw = _grads(_plan(s), x, w, g)
+    rx, rw = oracle.backward(x, w, g)
+    sx, sw = oracle.backward_scales(x, w, g)
+    ex = oracle.normalised_error(dx, rx, sx)
+    ew = oracle.normalised_error(dw, rw, sw)
+    assert ex[0] <= TOL, ("dx", ex)
+    assert ew[0] <= TOL, ("dw", ew)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_integer_exact(shape):
+    need_gpu()
+    s = wl.Shape(*shape)
+    x, w, rng = wl.draw_integer(s, seed=400 + sum(shape), xmax=3, wmax=3)
+    g = rng.integers(-3, 4, size=(s.batch, s.Ho, s.Wo, s.N)).astype(np.float32)
+    dx, dw = _grads(_plan(s), x, w, g)
+    rx, rw = oracle.backward(x, w, g)
+    np.testing.assert_array_equal(dx, rx.astype(np.float32))
+    np.testing.assert_array_equal(dw, rw.astype(np.float32))
+
+
+def test_one_gradient_at_a_time():
+    need_gpu()
+    s = wl.Shape(2, 33, 35, 8, 32, 5, 5)
+    x, w, rng = wl.draw_integer(s, seed=5, xmax=3, wmax=3)
+    g = rng.integers(-3, 4, size=(s.batch, s.Ho, s.Wo, s.N)).astype(np.float32)
+    plan = _plan(s)
+    rx, rw = oracle.backward(x, w, g)
+    dx, dw = _grads(plan, x, w, g, need_dw=False)
+    assert dw is None
+    np.testing.assert_array_equal(dx, rx.astype(np.float32))
+    dx, dw = _grads(plan, x, w, g, need_dx=False)
+    assert dx is None
+    np.testing.assert_array_equal(dw, rw.astype(np.float32))
+
+
+BX_CFGS = ["kc=8 s=4 mt=1 nt=1 wm=4 wn=1", "kc=16 s=2 mt=2 nt=1 wm=2 wn=1 ustage=3",
+           "kc=4 s=8 mt=1 nt=1 wm=2 wn=1 xcd=0", "kc=8 s=1 mt=1 nt=1 wm=4 wn=1"]
+BW_CFGS = ["rh=2 rw=32 mt=1 nt=2 wm=2 wn=4", "rh=8 rw=16 mt=2 nt=3 wm=1 wn=4 np=7",
+           "rh=4 rw=32 mt=1 nt=1 wm=2 wn=8 np=1", "rh=1 rw=64 mt=1 nt=4 wm=2 wn=2 gpad=0 xpad=0"]
+
+
+@pytest.mark.parametrize("cfg", BX_CFGS)
+def test_dx_configs_integer_exact(cfg):
+    need_gpu()
+    s = wl.Shape(2, 41, 67, 8, 64, 9, 9)
+    x, w, rng = wl.draw_integer(s, seed=9, xmax=2, wmax=2)
+    g = rng.integers(-2, 3, size=(s.batch, s.Ho, s.Wo, s.N)).astype(np.float32)
+    plan = _plan(s)
+    plan.set_config("backward_x", "algo=igemm " + cfg)
+    dx, _ = _grads(plan, x, w, g, need_dw=False)
+    rx, _ = oracle.backward(x, w, g, want_dw=False)
+    np.testing.assert_array_equal(dx, rx.astype(np.float32))
+
+
+@pytest.mark.parametrize("cfg", BW_CFGS)
+def test_dw_configs_integer_exact(cfg):
+    need_gpu()
+    s = wl.Shape(2, 41, 67, 8, 64, 9, 9)
+    x, w, rng = wl.draw_integer(s, seed=10, xmax=2, wmax=2)
+    g = rng.integers(-2, 3, size=(s.batch, s.Ho, s.Wo, s.N)).astype(np.float32)
+    plan = _plan(s)
+    plan.set_config("backward_w", "algo=dw " + cfg)
+    _, dw = _grads(plan, x, w, g, need_dx=False)
+    _, rw = oracle.backward(x, w, g, want_dx=False)
+    np.testing.assert_array_equal(dw, rw.astype(np.float32))
+
+
+def test_fp32_workload_full_size():
+    """256x256x8 input, 64 filters 9x9x8: full gradients against the oracle."""
+    need_gpu()
+    wk = wl.WORKLOADS["fp32"]
+    x, w, rng = wl.draw_single(wk.shape, wk.seed)
+    g = wl.draw_grad(wk.shape, rng)
+    dx, dw = _grads(_plan(wk.shape), x, w, g)
+    rx, rw = oracle.backward(x, w, g)
+    sx, sw = oracle.backward_scales(x, w, g)
+    ex = oracle.normalised_error(dx, rx, sx)
+    ew = oracle.normalised_error(dw, rw, sw)
+    print("fp32 workload dx %.3e dw %.3e" % (ex[0], ew[0]))
+    assert ex[0] <= TOL and ew[0] <= TOL
+
+
+def test_deterministic_repeat():
+    need_gpu()
+    s = wl.Shape(4, 64, 64, 16, 64, 7, 7)
+    x, w, rng = wl.draw_single(s, seed=11)
+    g = wl.draw_grad(s, rng)
+    plan = _plan(s)
+    a = _grads(plan, x, w, g)
+    b = _grads(plan, x, w, g)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_autograd_function_matches_oracle():
+    need_gpu()
+    import torch
+    from paper_0911_3456_amd import fbcorr
+    s = wl.Shape(2, 30, 28, 4, 12, 5, 3)
+    x, w, rng = wl.draw_single(s, seed=12)
+    g = wl.draw_grad(s, rng)
+    xt, wt, gt = to_dev(x, w, g)
+    xt.requires_grad_(True)
+    wt.requires_grad_(True)
+    y = fbcorr(xt, wt)
+    (y * gt).sum().backward()
+    torch.cuda.synchronize()
+    rx, rw = oracle.backward(x, w, g)
+    sx, sw = oracle.backward_scales(x, w, g)
+    assert oracle.normalised_error(host(y), oracle.forward(x, w), oracle.forward_scale(x, w))[0] <= TOL
+    assert oracle.normalised_error(host(xt.grad), rx, sx)[0] <= TOL
+    assert oracle.normalised_error(host(wt.grad), rw, sw)[0] <= TOL
+    # only one input requiring grad
+    xt2 = xt.detach().clone()
+    wt2 = wt.detach().clone().requires_grad_(True)
+    (fbcorr(xt2, wt2) * gt).sum().backward()
+    np.testing.assert_array_equal(host(wt2.grad), host(wt.grad))
+
+
+def _abs_scale_x(x, w, g, c):
+    """sum over the terms of dx[b,p,q,d] of |dy| |w| (error normaliser)."""
+    b, p, q, d = c
+    _, fh, fw, _ = w.shape
+    Ho, Wo = g.shape[1], g.shape[2]
+    tot = 0.0
+    for u in range(fh):
+        for v in range(fw):
+            i, j = p - u, q - v
+            if 0 <= i < Ho and 0 <= j < Wo:
+                tot += float(np.abs(g[b, i, j, :]).astype(np.float64) @ np.abs(w[:, u, v, d]).astype(np.float64))
+    return tot
+
+
+def _abs_scale_w(x, g, c, s):
+    """sum over the terms of dw[n,u,v,d] of |dy| |x| (error normaliser)."""
+    n, u, v, d = c
+    return float(np.sum(np.abs(g[..., n]).astype(np.float64) *
+                        np.abs(x[:, u:u + s.Ho, v:v + s.Wo, d]).astype(np.float64)))
+
+
+def test_differentiation_workload():
+    """32 inputs 128x128x16, 64 filters 7x7x16, dy ~ N(0,1): GPU gradients
+    against windowed FP64 central finite differences at 200 coordinates
+    (100 in x, 100 in w), and against the oracle's gradient on sampled
+    images (dX) and filters (dW)."""
+    need_gpu()
+    wk = wl.WORKLOADS["differentiation"]
+    s = wk.shape
+    x, w, rng = wl.draw_single(s, wk.seed)
+    g = wl.draw_grad(s, rng)
+    cx, cw = wl.fd_coordinates(s, rng, nx=100, nw=100)
+    dx, dw = _grads(_plan(s), x, w, g)
+    fdx = oracle.fd_grad_x(x, w, g, cx, h=1e-6)
+    fdw = oracle.fd_grad_w(x, w, g, cw, h=1e-6)
+    gx = np.array([dx[tuple(c)] for c in cx])
+    gw = np.array([dw[tuple(c)] for c in cw])
+    ax = np.array([_abs_scale_x(x, w, g, c) for c in cx])
+    aw = np.array([_abs_scale_w(x, g, c, s) for c in cw])
+    ex = np.max(np.abs(gx - fdx) / ax)
+    ew = np.max(np.abs(gw - fdw) / aw)
+    print("FD: dx %.3e dw %.3e" % (ex, ew))
+    assert ex <= TOL and ew <= TOL
+    # oracle gradient on two images (dX) and four filters (dW)
+    for b in (0, s.batch - 1):
+        rx, _ = oracle.backward(x[b:b + 1], w, g[b:b + 1], want_dw=False)
+        sx, _ = oracle.backward(np.abs(x[b:b + 1]), np.abs(w), np.abs(g[b:b + 1]), want_dw=False)
+        assert oracle.normalised_error(dx[b:b + 1], rx, sx)[0] <= TOL
+    for n in (0, 17, 40, s.N - 1):
+        _, rw = oracle.backward(x, w[n:n + 1], g[..., n:n + 1], want_dx=False)
+        _, sw = oracle.backward(np.abs(x), np.abs(w[n:n + 1]), np.abs(g[..., n:n + 1]), want_dx=False)
+        assert oracle.normalised_error(dw[n:n + 1], rw, sw)[0] <= TOL

@@ -1,0 +1,85 @@
+"""BF16/FP16 matrix-core forward against the FP64 oracle.
+
+Operands are rounded to nearest-even after a per-filter power-of-two scale
+(exact), products accumulate in fp32.  Bars: normalised error <= 1e-2
+against the oracle on the original fp32 operands (worst-case closed form for
+bf16: 2 * 2^-9 + fp32 accumulation ~ 3.9e-3), and ~fp32-accumulation level
+against an oracle run on the rounded operands.  On small integers the 16-bit
+path is exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from _gpu_util import forward_error, host, need_gpu, sample_sites, sampled_forward_error, to_dev
+
+pytestmark = pytest.mark.gpu
+
+LOWP_TOL = 1e-2
+BF16_BOUND = 2 * 2.0 ** -9 + 1e-5
+FP16_BOUND = 2 * 2.0 ** -11 + 1e-5
+
+
+def _plan(s, **kw):
+    from paper_0911_3456_amd import Plan
+    return Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, **kw)
+
+
+def _rounded_operands(x, w, prec):
+    sc = oracle.filter_pow2_scales(w)
+    rnd = oracle.round_to_bf16 if prec == "bf16" else oracle.round_to_fp16
+    xr = rnd(x).astype(np.float64)
+    wr = rnd((w.astype(np.float64) * sc[:, None, None, None]).astype(np.float32)).astype(np.float64)
+    wr = wr / sc[:, None, None, None]
+    return xr, wr
+
+
+SHAPES = [(1, 64, 64, 16, 128, 13, 13), (2, 40, 51, 8, 64, 9, 9), (1, 33, 70, 16, 32, 5, 5),
+          (1, 30, 30, 32, 48, 3, 3), (1, 20, 20, 4, 16, 5, 5)]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_lowp_error_bounds(shape, prec):
+    need_gpu()
+    s = wl.Shape(*shape)
+    x, w, _ = wl.draw_single(s, seed=500 + sum(shape))
+    y = host(_plan(s, precision=prec).forward(*to_dev(x, w)))
+    e, m, _ = forward_error(y, x, w)
+    bound = BF16_BOUND if prec == "bf16" else FP16_BOUND
+    print(prec, shape, "max %.3e mean %.3e (bound %.3e)" % (e, m, bound))
+    assert e <= LOWP_TOL and e <= bound
+    # against the oracle on the rounded operands: only accumulation error left
+    xr, wr = _rounded_operands(x, w, prec)
+    e2, _, _ = oracle.normalised_error(y, oracle.forward(xr, wr), oracle.forward_scale(xr, wr))
+    assert e2 <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_lowp_integer_exact(prec):
+    need_gpu()
+    s = wl.Shape(2, 45, 60, 16, 64, 7, 7)
+    x, w, _ = wl.draw_integer(s, seed=77)
+    w[3] = 0.0        # an all-zero filter (scale 1)
+    w[5] *= 0.125     # power-of-two scaled filter
+    y = host(_plan(s, precision=prec).forward(*to_dev(x, w)))
+    np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
+
+
+def test_precision_workload_sampled():
+    """512x512x16 input, 128 filters 13x13x16: fp32 (matrix-core and direct)
+    and bf16/fp16 outputs at sampled sites (and the four corners) against
+    the oracle."""
+    need_gpu()
+    wk = wl.WORKLOADS["precision"]
+    s = wk.shape
+    x, w, rng = wl.draw_single(s, wk.seed)
+    sites = sample_sites(np.random.default_rng(99), s, 400)
+    xt, wt = to_dev(x, w)
+    for prec, algo, tol in [("fp32", "igemm", 1e-5), ("fp32", "direct", 1e-5),
+                            ("bf16", "igemm", BF16_BOUND), ("fp16", "igemm", FP16_BOUND)]:
+        y = host(_plan(s, precision=prec, algo=algo).forward(xt, wt))
+        e, m, _ = sampled_forward_error(y, x, w, sites)
+        print("precision workload", prec, algo, "max %.3e mean %.3e" % (e, m))
+        assert e <= tol
