@@ -1,0 +1,240 @@
+"""Benchmark: filter-bank correlation forward + backward on one MI355X.
+
+A step is one pass of the hot path over one input: the forward correlation,
+the input gradient and the filter gradient, in fp32, on the 256x256x8 input
+with 64 filters 9x9x8 (the first shape of the paper's table "Performance of
+RTCG auto-tuning on 3D filter-bank convolutions").  Inputs are seeded
+synthetic data resident in GPU memory before timing starts.  value =
+3 * 2 * multiply-adds of one forward pass / seconds per step.
+
+Also printed in the same JSON line:
+  roofline      the dominant kernel's algorithmic flops per launch over its
+                average launch time (HIP events on the launch stream),
+                against the MI355X fp32 matrix peak; traffic from committed
+                rocprofv3 counter summaries when they match the current
+                kernel source.
+  cpu_baseline  the FP64 oracle timed on this host's cores (rank 0 only).
+  precision     the 512x512x16 / 128x13x13x16 forward: fp32 direct,
+                fp32 matrix-core, bf16 and fp16 matrix-core times and the
+                bf16/fp16 speedups (error bounds are enforced by the tests).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_MATRIX_PEAK_TFLOPS = 157.3     # MI355X dense fp32 matrix (and packed-vector) peak
+FP32_VALU_PEAK_TFLOPS = 78.6        # 256 CU * 64 FMA/clk * 2 flop * 2.4 GHz, no packed fp32
+BF16_MATRIX_PEAK_TFLOPS = 2500.0
+ROLES = ("forward", "backward_x", "backward_w")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tune", action="store_true", help="run the tuner for every role first")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--only", choices=["step", "forward", "backward_x", "backward_w"], default="step",
+                    help="profiling aid: time one role only")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_fingerprint(plan, role: str) -> str:
+    """Hash of the generated source and options of a role's main kernel."""
+    import paper_0911_3456_amd as fb
+    cfg = plan.get_config(role).split(" (")[0]
+    src, opts = fb.codegen(plan.desc, role, cfg)
+    return hashlib.sha256((src + "\0" + opts).encode()).hexdigest()[:16]
+
+
+def load_traffic(role: str, fingerprint: str, launches_bytes: float):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on exactly this kernel (same generated source and options)."""
+    path = os.path.join(ROOT, "profiles", "traffic_fp32_%s.json" % role)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("fingerprint") != fingerprint:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def time_steps(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(shape, x, w, g, budget_s: float = 20.0):
+    """The FP64 oracle (as it stands) on this host: forward + both gradients
+    of the same workload, repeated while within the time budget."""
+    import oracle
+    threads = oracle.max_threads()
+    reps, t_total = 0, 0.0
+    while reps == 0 or (t_total < budget_s * 0.5 and reps < 5):
+        t0 = time.perf_counter()
+        oracle.forward(x, w)
+        oracle.backward(x, w, g)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    flops = 3 * shape.flops * reps
+    return {"value": round(flops / t_total / 1e9, 4), "unit": "GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "full workload (forward + dX + dW, FP64 C loops, OpenMP), %d repetition(s), %.1f s"
+                      % (reps, t_total)}
+
+
+def precision_leg(steps: int, warmup: int):
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import Plan
+    wk = wl.WORKLOADS["precision"]
+    s = wk.shape
+    x, w, _ = wl.draw_single(s, wk.seed)
+    dev = torch.device("cuda", 0)
+    xt, wt = torch.from_numpy(x).to(dev), torch.from_numpy(w).to(dev)
+    out = {}
+    for prec, algo in (("fp32", "direct"), ("fp32", "igemm"), ("bf16", "igemm"), ("fp16", "igemm")):
+        plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, precision=prec, algo=algo, device=dev)
+        y = torch.empty(plan.y_shape, device=dev)
+        plan.enable_timing(True)
+        t = time_steps(lambda: plan.forward(xt, wt, y), max(3, steps // 5), warmup)
+        ms, calls = plan.read_timing()["forward"]
+        k_ms = ms / max(calls, 1)
+        out["%s_%s" % (prec, algo)] = {"ms": round(t * 1e3, 4), "kernel_ms": round(k_ms, 4),
+                                        "tflops": round(s.flops / k_ms / 1e9, 2),
+                                        "config": plan.get_config("forward")}
+        plan.close()
+    base = out["fp32_direct"]["ms"]
+    for k in ("fp32_igemm", "bf16_igemm", "fp16_igemm"):
+        out[k]["speedup_vs_fp32_direct"] = round(base / out[k]["ms"], 3)
+    out["workload"] = "512x512x16 input, 128 filters 13x13x16 (forward only)"
+    out["bf16_frac_of_peak"] = round(out["bf16_igemm"]["tflops"] / BF16_MATRIX_PEAK_TFLOPS, 4)
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import Plan
+
+    wk = wl.WORKLOADS["fp32"]
+    s = wk.shape
+    x, w, rng = wl.draw_single(s, wk.seed)
+    g = wl.draw_grad(s, rng)
+    dev = torch.device("cuda", 0)
+    xt, wt, gt = (torch.from_numpy(a).to(dev) for a in (x, w, g))
+    t0 = time.perf_counter()
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, device=dev)
+    y = torch.empty(plan.y_shape, device=dev)
+    dx = torch.empty_like(xt)
+    dw = torch.empty_like(wt)
+    plan.backward(xt, wt, gt, dx=dx, dw=dw)        # compiles the gradient roles
+    torch.cuda.synchronize()
+    log("plan + compile: %.2f s" % (time.perf_counter() - t0))
+    tune_reports = {}
+    if args.tune:
+        for role in ROLES:
+            buf = y if role == "forward" else gt.clone()
+            rep = plan.tune(xt, wt, buf, role=role, warmup=2, reps=10, with_direct=(role == "forward"))
+            tune_reports[role] = {"default_ms": round(rep["default_ms"], 4), "best_ms": round(rep["best_ms"], 4),
+                                  "boost": round(rep["default_ms"] / rep["best_ms"] - 1, 4),
+                                  "tried": rep["n_tried"], "compiled": rep["n_compiled"]}
+            log("tuned", role, rep["best_cfg"], "%.4f ms (default %.4f ms)" % (rep["best_ms"], rep["default_ms"]))
+
+    def step():
+        plan.forward(xt, wt, y)
+        plan.backward(xt, wt, gt, dx=dx, dw=dw)
+
+    def only(role):
+        if role == "forward":
+            return lambda: plan.forward(xt, wt, y)
+        if role == "backward_x":
+            return lambda: plan.backward(xt, wt, gt, need_dw=False, dx=dx)
+        return lambda: plan.backward(xt, wt, gt, need_dx=False, dw=dw)
+
+    fn = step if args.only == "step" else only(args.only)
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    plan.read_timing(reset=True)
+    plan.enable_timing(True)
+    sec = time_steps(fn, args.steps, 0)
+    plan.enable_timing(False)
+    timing = plan.read_timing(reset=True)
+    flops_step = 3 * s.flops if args.only == "step" else s.flops
+    value = flops_step / sec / 1e9
+
+    kern = {r: timing[r][0] / timing[r][1] for r in ROLES if timing[r][1] > 0}
+    dom = max(kern, key=kern.get)
+    achieved = s.flops / (kern[dom] * 1e-3) / 1e12
+    fp = kernel_fingerprint(plan, dom)
+    traffic = load_traffic(dom, fp, None)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_MATRIX_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MATRIX_PEAK_TFLOPS, 4),
+                "traffic": traffic, "kernel": dom, "kernel_ms": round(kern[dom], 5),
+                "per_role_kernel_ms": {r: round(v, 5) for r, v in kern.items()},
+                "per_role_tflops": {r: round(s.flops / (v * 1e-3) / 1e12, 3) for r, v in kern.items()},
+                "fingerprint": fp}
+
+    result = {
+        "metric": "filterbank-correlation GFLOP/s fwd+bwd, % roofline; BF16-MFMA vs FP32 at stated err",
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded uniform[-1,1] input, normalised filters, N(0,1) upstream gradient)",
+        "config": {"workload": "fp32: input 256x256x8, 64 filters 9x9x8, valid output 248x248x64, "
+                               "step = forward + dX + dW",
+                   "role": args.only,
+                   "kernels": {r: plan.get_config(r) for r in ROLES}},
+        "roofline": roofline,
+    }
+    if tune_reports:
+        result["tune"] = tune_reports
+    if not args.no_precision and args.only == "step":
+        log("precision leg ...")
+        result["precision"] = precision_leg(args.steps, args.warmup)
+    if not args.no_cpu_baseline and args.only == "step":
+        log("cpu baseline (FP64 oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(s, x, w, g)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

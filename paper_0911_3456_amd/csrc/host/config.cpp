@@ -131,8 +131,8 @@ static void opt(std::vector<std::string>& o, const char* k, long v) {
 }
 
 // igemm: valid correlation over a virtually padded input (see igemm.hip).
-static bool geom_igemm(const Config& c, int batch, int hi, int wi, int cin, int cout, int fh, int fw,
-                       int padh, int padw, int dt, const DeviceInfo& di, LaunchGeom& g,
+static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, int wi, int cin, int cout,
+                       int fh, int fw, int padh, int padw, int dt, const DeviceInfo& di, LaunchGeom& g,
                        KernelSource& ks, std::string& err) {
     const int kc = c.get("kc"), s = c.get("s"), mt = c.get("mt"), nt = c.get("nt");
     const int wm = c.get("wm"), wn = c.get("wn"), xpad = c.get("xpad"), wpad = c.get("wpad");
@@ -170,10 +170,11 @@ static bool geom_igemm(const Config& c, int batch, int hi, int wi, int cin, int 
     g.grid_y = 1;
     g.threads = threads;
     g.lds = (int)lds;
-    ks.name = "fbcorr_igemm";
+    ks.name = kname;
     ks.file = "igemm";
     ks.source = template_source("igemm");
     ks.options.clear();
+    ks.options.push_back(std::string("-DFB_KNAME=") + kname);
     opt(ks.options, "BATCH", batch); opt(ks.options, "FH", fh); opt(ks.options, "FW", fw);
     opt(ks.options, "CIN", cin); opt(ks.options, "COUT", cout);
     opt(ks.options, "HI", hi); opt(ks.options, "WI", wi); opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
@@ -325,7 +326,8 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
             if (dt != 0) { err = "the direct kernel is fp32 only"; return false; }
             if (!geom_direct(c, d, di, rb.main_geom, rb.main, err)) return false;
         } else if (c.algo == "igemm") {
-            if (!geom_igemm(c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di, rb.main_geom, rb.main, err))
+            if (!geom_igemm("fbcorr_fwd_igemm", c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di,
+                            rb.main_geom, rb.main, err))
                 return false;
         } else {
             err = "forward role needs algo=igemm or algo=direct";
@@ -347,7 +349,7 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
         if (c.algo != "igemm") { err = "input-gradient role needs algo=igemm"; return false; }
         // dx = valid correlation of dy (padded by fh-1, fw-1) with flipped,
         // transposed filters: CIN = N, COUT = D, input extent Ho x Wo.
-        if (!geom_igemm(c, d.batch, ho, wo, d.N, d.D, d.fh, d.fw, d.fh - 1, d.fw - 1, 0, di,
+        if (!geom_igemm("fbcorr_dx_igemm", c, d.batch, ho, wo, d.N, d.D, d.fh, d.fw, d.fh - 1, d.fw - 1, 0, di,
                         rb.main_geom, rb.main, err))
             return false;
         KernelSource ks = util_source("fbcorr_flip_filters", "FLIP_FILTERS");

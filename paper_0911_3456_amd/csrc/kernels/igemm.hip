@@ -116,8 +116,13 @@ __device__ __forceinline__ elem_t to_elem(float v) {
 #endif
 }
 
+// The symbol name is chosen by the generator (forward and input-gradient
+// instances get distinct names, so profiles tell them apart).
+#ifndef FB_KNAME
+#define FB_KNAME fbcorr_igemm
+#endif
 extern "C" __global__ void __launch_bounds__(NTHREADS)
-fbcorr_igemm(const float* __restrict__ I, const elem_t* __restrict__ Wt,
+FB_KNAME(const float* __restrict__ I, const elem_t* __restrict__ Wt,
              const float* __restrict__ UNSCALE, float* __restrict__ O)
 {
     __shared__ __attribute__((aligned(16))) elem_t tile[TILE_ELEMS];
