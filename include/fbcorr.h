@@ -114,7 +114,8 @@ typedef struct fbcorr_tune_opts {
     int32_t warmup, reps;
     int32_t max_candidates;
     int32_t role;      /* fbcorr_role to tune */
-    uint32_t flags;    /* bit 0: also try the DIRECT algorithm for the forward role */
+    uint32_t flags;    /* bit 0: also try the DIRECT algorithm for the forward role;
+                          bit 1: record the winner in the tuning database */
 } fbcorr_tune_opts;
 
 typedef struct fbcorr_tune_report {
@@ -128,8 +129,13 @@ typedef struct fbcorr_tune_report {
  * fbcorr_plan: validates the descriptor (Sec. 6.2's operation; any dim <= 0
  * -> INVALID_ARGUMENT, fh > H or fw > W -> SHAPE), selects default kernel
  * configurations, generates their source and compiles them with hiprtc for
- * `device` (cached), and loads them.  The plan owns host state and modules;
- * *out is written only on success. */
+ * `device` (cached), and loads them.  Default configurations come from the
+ * tuning database (Sec. 6.2: ship a database of configurations per
+ * platform; file tuning_db.txt beside the library or $FBCORR_TUNING_DB,
+ * lines "<arch> <role> <precision> <batch> <H> <W> <D> <N> <fh> <fw> :
+ * <config>"), else from built-in heuristics.  The plan owns host state; the
+ * compiled modules belong to the process-wide cache.  *out is written only
+ * on success. */
 FBCORR_API fbcorr_status fbcorr_plan(const fbcorr_desc* desc, int device, fbcorr_plan_t* out);
 
 /* Releases a plan (Sec. 5: resources can be released explicitly).  All work
@@ -137,7 +143,7 @@ FBCORR_API fbcorr_status fbcorr_plan(const fbcorr_desc* desc, int device, fbcorr
 FBCORR_API fbcorr_status fbcorr_plan_destroy(fbcorr_plan_t plan);
 
 /* Bytes of workspace needed by a pass: pass 0 = forward, pass 1 = backward
- * (both gradients).  The value depends on the plan's current configuration
+ * (both gradients), pass 2 = fbcorr_tune (any role).  The value depends on the plan's current configuration
  * and may change after fbcorr_tune or fbcorr_plan_set_config. */
 FBCORR_API fbcorr_status fbcorr_workspace_size(fbcorr_plan_t plan, int pass, size_t* bytes);
 

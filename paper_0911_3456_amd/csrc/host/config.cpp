@@ -80,10 +80,40 @@ Config default_igemm(int cin, int cout, bool lowp) {
     c.algo = "igemm";
     const int s = pick_shift(cout);
     const int cols = cout * s;
-    int nt = cols >= 64 ? 2 : 1;
-    c.v = {{"kc", pick_kc(cin, lowp)}, {"s", s}, {"mt", 1}, {"nt", nt}, {"wm", 4}, {"wn", 1},
-           {"xpad", lowp ? 8 : 4}, {"wpad", lowp ? 8 : 4}, {"ustage", 1}, {"xcd", 1}};
+    const int nt = cols >= 64 ? 2 : 1;
+    const int kc = pick_kc(cin, lowp);
+    const int nchunk = (cin + kc - 1) / kc;
+    c.v = {{"kc", kc}, {"s", s}, {"mr", s >= 2 ? 4 : 1}, {"mt", 1}, {"nt", nt}, {"wm", s >= 2 ? 1 : 4},
+           {"wn", 1}, {"ks", s >= 2 ? std::min(4, nchunk) : 1}, {"xpad", lowp ? 8 : 4},
+           {"wpad", lowp ? 8 : 4}, {"ustage", 1}, {"xcd", 1}};
     return c;
+}
+
+// Variants of a default that use fewer resources, tried in order until one
+// fits the device.
+static std::vector<Config> shrink_sequence(const Config& base) {
+    std::vector<Config> out{base};
+    Config c = base;
+    for (int step = 0; step < 16; ++step) {
+        if (c.algo == "igemm") {
+            if (c.v["ks"] > 1) c.v["ks"] /= 2;
+            else if (c.v["kc"] > 4 && c.v["kc"] % 2 == 0) c.v["kc"] /= 2;
+            else if (c.v["nt"] > 1) c.v["nt"] /= 2;
+            else if (c.v["wm"] > 1) c.v["wm"] /= 2;
+            else if (c.v["mr"] > 1) c.v["mr"] /= 2;
+            else if (c.v["kc"] > 1) c.v["kc"] = (c.v["kc"] + 1) / 2;
+            else break;
+        } else if (c.algo == "direct") {
+            if (c.v["th"] > 1) c.v["th"] /= 2;
+            else break;
+        } else {
+            if (c.v["rh"] > 1) c.v["rh"] /= 2;
+            else if (c.v["rw"] > 8) c.v["rw"] /= 2;
+            else break;
+        }
+        out.push_back(c);
+    }
+    return out;
 }
 
 Config default_direct(const fbcorr_desc& d) {
@@ -109,7 +139,7 @@ Config default_dw(const fbcorr_desc& d, int cus) {
     return c;
 }
 
-Config default_config(const fbcorr_desc& d, int role, int cus) {
+static Config heuristic_config(const fbcorr_desc& d, int role, int cus) {
     const bool lowp = d.precision != FBCORR_FP32;
     switch (role) {
     case FBCORR_ROLE_FORWARD:
@@ -136,23 +166,27 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
                        KernelSource& ks, std::string& err) {
     const int kc = c.get("kc"), s = c.get("s"), mt = c.get("mt"), nt = c.get("nt");
     const int wm = c.get("wm"), wn = c.get("wn"), xpad = c.get("xpad"), wpad = c.get("wpad");
-    const int ustage = c.get("ustage"), xcd = c.get("xcd");
-    if (kc < 1 || s < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || xpad < 0 || wpad < 0 || ustage < 1) {
+    const int ustage = std::min(c.get("ustage"), fh), xcd = c.get("xcd");
+    const int mr = c.get("mr"), ksp = c.get("ks");
+    if (kc < 1 || s < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || xpad < 0 || wpad < 0 || ustage < 1 ||
+        mr < 1 || ksp < 1) {
         err = "igemm: every knob must be positive"; return false;
     }
     if (s != 1 && s != 2 && s != 4 && s != 8) { err = "igemm: s must be 1, 2, 4 or 8"; return false; }
-    const int threads = wm * wn * 64;
+    if (32 % mr) { err = "igemm: mr must divide 32"; return false; }
+    const int threads = wm * wn * ksp * 64;
     if (threads > std::min(1024, di.max_threads)) { err = "igemm: too many threads"; return false; }
     if (mt * nt > 8) { err = "igemm: more than 8 accumulator tiles per wave"; return false; }
     const int ncol = wn * nt * 32;
     if (ncol % s) { err = "igemm: columns must split evenly into shifts"; return false; }
     const int cb = ncol / s;
+    const int mc = 32 / mr;
     const int ho = hi + 2 * padh - fh + 1, wo = wi + 2 * padw - fw + 1;
     const int esz = dt == 0 ? 4 : 2;
     const int runit = dt == 0 ? 8 : 16;
     const int krraw = (fw + s - 1) * kc;
     const int kr = round_up(krraw, runit);
-    const int rowe = 31 * s * kc + kr;
+    const int rowe = (mc - 1) * s * kc + kr;
     const int rows = rowe + xpad;
     const int wrs = kr + wpad;
     int av;
@@ -160,11 +194,15 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     else av = ((s * kc) % 8 == 0) ? 8 : (((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1));
     if (rows % av) { err = "igemm: xpad breaks A-read alignment"; return false; }
     if (dt == 0 ? (wrs % 4) : (wrs % 8)) { err = "igemm: wpad breaks B-read alignment"; return false; }
-    const int th = wm * mt;
+    const int th = wm * mt * mr;
     const int tr = th + fh - 1;
-    const long lds = (long)(tr * rows + std::min(ustage, fh) * ncol * wrs) * esz;
+    const long tile = round_up(tr * rows, 8);
+    const long wsl = (long)ustage * ncol * wrs;
+    const long group = (tile + 2 * wsl + 7) / 8 * 8;
+    const long red = (long)(ksp - 1) * wm * wn * mt * nt * 16 * 64 * 4;
+    const long lds = std::max(ksp * group * esz, red);
     if (lds > di.lds_per_block) { err = "igemm: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
-    const long grid = (long)cdiv(wo, 32 * s) * cdiv(ho, th) * cdiv(cout, cb) * batch;
+    const long grid = (long)cdiv(wo, s * mc) * cdiv(ho, th) * cdiv(cout, cb) * batch;
     if (grid <= 0 || grid > 0x7fffffffL) { err = "igemm: grid out of range"; return false; }
     g.grid_x = (int)grid;
     g.grid_y = 1;
@@ -179,10 +217,11 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "CIN", cin); opt(ks.options, "COUT", cout);
     opt(ks.options, "HI", hi); opt(ks.options, "WI", wi); opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
     opt(ks.options, "PADH", padh); opt(ks.options, "PADW", padw);
-    opt(ks.options, "KC", kc); opt(ks.options, "S", s); opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
-    opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "DT", dt);
+    opt(ks.options, "KC", kc); opt(ks.options, "S", s); opt(ks.options, "MR", mr);
+    opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
+    opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "KS", ksp); opt(ks.options, "DT", dt);
     opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad);
-    opt(ks.options, "USTAGE", std::min(ustage, fh)); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    opt(ks.options, "USTAGE", ustage); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
     return true;
 }
 
@@ -297,7 +336,7 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
 
 static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
-        {"igemm", {"kc", "s", "mt", "nt", "wm", "wn", "xpad", "wpad", "ustage", "xcd"}},
+        {"igemm", {"kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd"}},
         {"dw", {"rh", "rw", "mt", "nt", "wm", "wn", "gpad", "xpad", "np"}},
     };
@@ -375,6 +414,37 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
     }
     err = "unknown role";
     return false;
+}
+
+Config default_config(const fbcorr_desc& d, int role, const DeviceInfo& di) {
+    std::string text;
+    if (tuning_db_lookup(di.arch, role, d, text)) {
+        Config c = heuristic_config(d, role, di.cus);
+        std::string err;
+        Config probe;
+        probe.algo = c.algo;
+        if (parse_config(text, probe, err)) {
+            // start from the chosen algorithm's heuristic and apply the entry
+            Config base = probe.algo == c.algo ? c
+                          : (probe.algo == "direct" ? default_direct(d)
+                                                    : default_igemm(role == FBCORR_ROLE_BACKWARD_X ? d.N : d.D,
+                                                                    role == FBCORR_ROLE_BACKWARD_X ? d.D : d.N,
+                                                                    d.precision != FBCORR_FP32));
+            RoleBuild rb;
+            if (parse_config(text, base, err) && build_role(d, role, base, di, rb, err)) return base;
+        }
+    }
+    return heuristic_default(d, role, di);
+}
+
+Config heuristic_default(const fbcorr_desc& d, int role, const DeviceInfo& di) {
+    const Config h = heuristic_config(d, role, di.cus);
+    for (const Config& c : shrink_sequence(h)) {
+        RoleBuild rb;
+        std::string err;
+        if (build_role(d, role, c, di, rb, err)) return c;
+    }
+    return h;   // nothing fits: the caller reports the heuristic's error
 }
 
 }  // namespace fbc

@@ -25,7 +25,18 @@ struct RoleBuild {
     int np = 0;                             // filter-gradient partial count
 };
 
-Config default_config(const fbcorr_desc& d, int role, int cus);
+// Default configuration of a role: the tuning database's entry for this
+// hardware and problem if there is one, else the hand-written heuristic
+// (shrunk until it fits the device).
+Config default_config(const fbcorr_desc& d, int role, const DeviceInfo& di);
+Config heuristic_default(const fbcorr_desc& d, int role, const DeviceInfo& di);
+
+// tuning_db.cpp
+std::string tuning_db_path();
+bool tuning_db_lookup(const std::string& arch, int role, const fbcorr_desc& d, std::string& cfg);
+bool tuning_db_record(const std::string& arch, int role, const fbcorr_desc& d, const std::string& cfg,
+                      std::string& err);
+void tuning_db_reload();
 Config default_igemm(int cin, int cout, bool lowp);
 Config default_direct(const fbcorr_desc& d);
 bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,

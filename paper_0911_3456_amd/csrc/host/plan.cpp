@@ -166,7 +166,7 @@ size_t backward_ws(const Plan* p, size_t* off_w) {
 
 fbcorr_status ensure_role(Plan* p, int role) {
     if (p->have[role]) return FBCORR_OK;
-    return compile_role(p, role, default_config(p->desc, role, p->dev.cus));
+    return compile_role(p, role, default_config(p->desc, role, p->dev));
 }
 
 }  // namespace fbc
@@ -218,7 +218,7 @@ fbcorr_status fbcorr_plan(const fbcorr_desc* desc, int device, fbcorr_plan_t* ou
     st = device_info(device, p->dev);
     if (st != FBCORR_OK) return st;
     DeviceGuard g(device);
-    st = compile_role(p.get(), FBCORR_ROLE_FORWARD, default_config(*desc, FBCORR_ROLE_FORWARD, p->dev.cus));
+    st = compile_role(p.get(), FBCORR_ROLE_FORWARD, default_config(*desc, FBCORR_ROLE_FORWARD, p->dev));
     if (st != FBCORR_OK) return st;
     *out = reinterpret_cast<fbcorr_plan_t>(p.release());
     return FBCORR_OK;
@@ -344,7 +344,7 @@ fbcorr_status fbcorr_plan_set_config(fbcorr_plan_t plan, int role, const char* c
     FBC_RETURN_IF(p->batched, FBCORR_ERR_UNSUPPORTED, "batched plans are configured at plan time");
     FBC_RETURN_IF(role < 0 || role >= FBCORR_ROLE_COUNT, FBCORR_ERR_INVALID_ARGUMENT, "unknown role");
     DeviceGuard g(p->device);
-    Config c = default_config(p->desc, role, p->dev.cus);
+    Config c = default_config(p->desc, role, p->dev);
     // "algo=direct" alone selects that algorithm's defaults
     std::string text(cfg), err;
     if (text.find("algo=direct") != std::string::npos && role == FBCORR_ROLE_FORWARD) c = default_direct(p->desc);
@@ -410,7 +410,7 @@ static fbcorr_status offline_build(const fbcorr_desc* desc, int role, const char
     if (st != FBCORR_OK) return st;
     FBC_RETURN_IF(role < 0 || role >= FBCORR_ROLE_COUNT, FBCORR_ERR_INVALID_ARGUMENT, "unknown role");
     DeviceInfo di = offline_device(arch);
-    Config c = default_config(*desc, role, di.cus);
+    Config c = default_config(*desc, role, di);
     std::string err;
     if (cfg) {
         std::string text(cfg);

@@ -66,29 +66,46 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         const bool lp = lowp && role == FBCORR_ROLE_FORWARD;
         std::vector<int> kcs = {base.get("kc")};
         for (int kc : {4, 8, 16, 32})
-            if (kc <= cin && cin % kc == 0 && (!lp || kc % 8 == 0)) kcs.push_back(kc);
+            if (kc <= cin && (cin % kc == 0 || kc == 8) && (!lp || kc % 8 == 0) && kc != base.get("kc"))
+                kcs.push_back(kc);
         std::vector<int> ss = {base.get("s")};
         if (base.get("s") > 1) ss.push_back(base.get("s") / 2);
-        // (mt, nt, wm, wn): per-wave tiles and waves per workgroup
+        // (mt, nt, wm, wn): per-wave tiles and waves per contraction group
         const int shapes[][4] = {{1, 1, 4, 1}, {1, 2, 4, 1}, {2, 1, 2, 2}, {2, 2, 2, 1}, {1, 2, 2, 2},
-                                 {2, 2, 4, 1}, {1, 4, 4, 1}, {2, 2, 2, 2}, {4, 2, 1, 1}, {1, 1, 8, 1}};
+                                 {2, 2, 4, 1}, {1, 4, 4, 1}, {2, 2, 2, 2}, {4, 2, 1, 1}, {1, 1, 8, 1},
+                                 {1, 1, 1, 1}, {2, 1, 1, 1}, {1, 2, 1, 1}, {2, 2, 1, 1}, {1, 1, 2, 1}};
+        std::vector<Config> grid;
         for (int kc : kcs)
             for (int s : ss)
-                for (auto& sh : shapes)
-                    for (int us : {1, 3})
-                        for (int pad : {0, 1}) {
-                            Config c = base;
-                            c.v["kc"] = kc;
-                            c.v["s"] = s;
-                            c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
-                            // skip tiles whose columns exceed what the channels can fill
-                            if (sh[1] * sh[3] * 32 > std::max(32, ((cout * s + 31) / 32) * 32)) continue;
-                            c.v["ustage"] = us;
-                            const int unit = lp ? 8 : 4;
-                            c.v["xpad"] = pad * unit;
-                            c.v["wpad"] = pad * unit;
-                            add(out, seen, c);
-                        }
+                for (int mr : {1, 2, 4, 8})
+                    for (auto& sh : shapes)
+                        for (int ksp : {1, 2, 4})
+                            for (int us : {1, 3})
+                                for (int pad : {0, 1}) {
+                                    Config c = base;
+                                    c.v["kc"] = kc;
+                                    c.v["s"] = s;
+                                    c.v["mr"] = mr;
+                                    c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
+                                    c.v["ks"] = ksp;
+                                    // skip tiles whose columns exceed what the channels can fill
+                                    if (sh[1] * sh[3] * 32 > std::max(32, ((cout * s + 31) / 32) * 32)) continue;
+                                    if (sh[0] * sh[1] * sh[2] * sh[3] * ksp > 16) continue;
+                                    c.v["ustage"] = us;
+                                    const int unit = lp ? 8 : 4;
+                                    c.v["xpad"] = pad * unit;
+                                    c.v["wpad"] = pad * unit;
+                                    grid.push_back(c);
+                                }
+        // a coarse, deterministic subsample of the full grid (Fisher-Yates
+        // with a fixed LCG), the default first
+        uint64_t st = 0x9E3779B97F4A7C15ull;
+        for (size_t i = grid.size(); i > 1; --i) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            std::swap(grid[i - 1], grid[(st >> 33) % i]);
+        }
+        add(out, seen, base);
+        for (auto& c : grid) add(out, seen, c);
         if (with_direct && role == FBCORR_ROLE_FORWARD && !lowp) {
             const Config db = default_direct(d);
             for (int th : {4, 8, 16})
@@ -107,7 +124,7 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                 }
         }
     } else {
-        const Config base = default_config(d, role, 256);
+        const Config base = default_config(d, role, DeviceInfo{"gfx950", 256, 160 * 1024, 1024});
         const int shapes[][4] = {{1, 3, 2, 4}, {1, 2, 2, 4}, {2, 3, 1, 4}, {1, 4, 2, 2}, {2, 2, 1, 8},
                                  {1, 3, 2, 2}, {2, 4, 1, 4}, {1, 1, 2, 8}};
         for (auto& sh : shapes)
@@ -253,7 +270,7 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         memset(&rep, 0, sizeof rep);
 
         // Default variant: the reference for the gate and the "default" time.
-        const Config dcfg = default_config(d, role, p->dev.cus);
+        const Config dcfg = heuristic_default(d, role, p->dev);
         RoleBuild drb;
         std::string err;
         FBC_RETURN_IF(!build_role(d, role, dcfg, p->dev, drb, err), FBCORR_ERR_UNSUPPORTED, "default: " + err);
@@ -336,6 +353,10 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         snprintf(rep.best_cfg, sizeof rep.best_cfg, "%s", chosen.str().c_str());
         st = compile_role(p, role, chosen);
         if (st != FBCORR_OK) return st;
+        if (opts && (opts->flags & 2u)) {
+            std::string e2;
+            FBC_RETURN_IF(!tuning_db_record(p->dev.arch, role, d, chosen.str(), e2), FBCORR_ERR_INTERNAL, e2);
+        }
         if (report) *report = rep;
         return FBCORR_OK;
     } catch (const std::exception& e) {
