@@ -143,3 +143,23 @@ def test_plan_without_device_reports_no_device():
     st = lib.fbcorr_plan(ctypes.byref(d), 0, ctypes.byref(h))
     assert nat.STATUS_NAMES[st] == "FBCORR_ERR_NO_DEVICE"
     assert not h.value
+
+
+def test_gpu_test_configurations_are_valid():
+    """Every explicit configuration the GPU tests install fits the device
+    limits (checked here, on the host, before any GPU run)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import paper_0911_3456_amd as fb
+    import test_gpu_backward as tb
+    import test_gpu_forward as tf
+    d = fb.make_desc(2, 45, 77, 8, 64, 9, 9)
+    for c in tf.IGEMM_CFGS:
+        fb.codegen(d, "forward", "algo=igemm " + c)
+    for c in tf.DIRECT_CFGS:
+        fb.codegen(d, "forward", "algo=direct " + c)
+    d = fb.make_desc(2, 41, 67, 8, 64, 9, 9)
+    for c in tb.BX_CFGS:
+        fb.codegen(d, "backward_x", "algo=igemm " + c)
+    for c in tb.BW_CFGS:
+        fb.codegen(d, "backward_w", "algo=dw " + c)

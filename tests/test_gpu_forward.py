@@ -85,8 +85,8 @@ def test_random_fp32(shape):
 
 IGEMM_CFGS = [
     "kc=8 s=1 mr=4 mt=1 nt=2 wm=2 wn=1 ks=2",
-    "kc=4 s=2 mr=2 mt=2 nt=1 wm=1 wn=2 ks=4 ustage=2",
-    "kc=8 s=1 mr=8 mt=1 nt=1 wm=1 wn=2 ks=3 ustage=4 xpad=0",
+    "kc=4 s=2 mr=2 mt=2 nt=1 wm=1 wn=2 ks=2 ustage=1",
+    "kc=8 s=1 mr=8 mt=1 nt=1 wm=1 wn=2 ks=3 ustage=1 xpad=0",
     "kc=2 s=1 mr=32 mt=1 nt=2 wm=2 wn=1 ks=1",
     "kc=4 s=1 mt=1 nt=2 wm=4 wn=1",
     "kc=8 s=1 mt=2 nt=2 wm=2 wn=1 ustage=3",
