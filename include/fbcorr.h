@@ -188,7 +188,8 @@ FBCORR_API fbcorr_status fbcorr_plan_batched(int32_t count, const fbcorr_desc* d
 
 /* fbcorr_forward_batched: xs, ws_, ys are DEVICE arrays of `count` device
  * pointers (the i-th problem's x, w, y).  use_graph != 0 captures the launch
- * into a HIP graph on the first call per stream and replays it afterwards;
+ * into a HIP graph on the first call per stream (which must be a created
+ * stream, not the null stream) and replays it afterwards;
  * the pointer arrays are then read at replay time, so their contents may
  * change between calls but their addresses and the workspace must not. */
 FBCORR_API fbcorr_status fbcorr_forward_batched(fbcorr_plan_t plan, const float* const* xs,
@@ -223,6 +224,12 @@ FBCORR_API fbcorr_status fbcorr_codegen(const fbcorr_desc* desc, int role, const
  * hiprtc, without a device, and report the code-object size.  Host-only. */
 FBCORR_API fbcorr_status fbcorr_compile_check(const fbcorr_desc* desc, int role, const char* cfg,
                                    const char* arch, size_t* code_bytes);
+
+/* Generate and compile the persistent batched kernel for `count`
+ * descriptors (as fbcorr_plan_batched would) for an architecture name,
+ * without a device.  Host-only. */
+FBCORR_API fbcorr_status fbcorr_compile_check_batched(int32_t count, const fbcorr_desc* descs, const char* arch,
+                                                      size_t* code_bytes);
 
 /* In-process code-object cache statistics (hits, misses, entries). */
 FBCORR_API fbcorr_status fbcorr_cache_stats(int64_t* hits, int64_t* misses, int64_t* entries);

@@ -31,7 +31,8 @@ EXPORTS = (
     "fbcorr_plan", "fbcorr_plan_destroy", "fbcorr_workspace_size", "fbcorr_forward",
     "fbcorr_backward", "fbcorr_tune", "fbcorr_plan_batched", "fbcorr_forward_batched",
     "fbcorr_plan_get_config", "fbcorr_plan_set_config", "fbcorr_plan_enable_timing",
-    "fbcorr_plan_read_timing", "fbcorr_codegen", "fbcorr_compile_check", "fbcorr_cache_stats",
+    "fbcorr_plan_read_timing", "fbcorr_codegen", "fbcorr_compile_check", "fbcorr_compile_check_batched",
+    "fbcorr_cache_stats",
     "fbcorr_last_error", "fbcorr_status_string", "fbcorr_version",
 )
 
@@ -99,6 +100,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(sz), ctypes.c_char_p, ctypes.POINTER(sz)]
     lib.fbcorr_compile_check.argtypes = [ctypes.POINTER(Desc), ctypes.c_int, ctypes.c_char_p,
                                          ctypes.c_char_p, ctypes.POINTER(sz)]
+    lib.fbcorr_compile_check_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), ctypes.c_char_p,
+                                                 ctypes.POINTER(sz)]
     lib.fbcorr_cache_stats.argtypes = [ctypes.POINTER(ctypes.c_int64)] * 3
     lib.fbcorr_last_error.restype = ctypes.c_char_p
     lib.fbcorr_last_error.argtypes = []
@@ -139,6 +142,16 @@ def compile_check(desc: Desc, role: str = "forward", cfg: str | None = None, arc
     n = ctypes.c_size_t(0)
     check(lib.fbcorr_compile_check(ctypes.byref(desc), ROLES[role], cfg.encode() if cfg else None,
                                    arch.encode(), ctypes.byref(n)))
+    return n.value
+
+
+def compile_check_batched(descs, arch: str = "gfx950") -> int:
+    """Generate and compile the persistent batched kernel for a list of
+    descriptors without a device."""
+    lib = load()
+    arr = (Desc * len(descs))(*descs)
+    n = ctypes.c_size_t(0)
+    check(lib.fbcorr_compile_check_batched(len(descs), arr, arch.encode(), ctypes.byref(n)))
     return n.value
 
 

@@ -1,24 +1,416 @@
-// Many uneven images in one persistent launch (placeholder until the
-// persistent kernel lands: the entry points report UNSUPPORTED).
+// Many uneven images in one persistent launch.
+//
+// Every distinct problem key (fh, fw, D, N) of the batch gets one tile
+// configuration, and the generator emits one kernel holding exactly those
+// variants (Sec. 4.2: generate code for exactly one purpose): the
+// implicit-GEMM body section is pasted once per key with that key's constants
+// substituted and the image extents left run-time, followed by a dispatch
+// loop.  At plan time the host builds a work table of (variant, image, tile)
+// items sorted by cost, largest first; at run time each persistent
+// workgroup takes the next item from an integer counter until the table is
+// exhausted.  The launch (a counter-reset kernel plus the persistent kernel)
+// can be captured once into a HIP graph per stream and replayed.
 #include "plan.h"
 
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <set>
+#include <sstream>
+
 namespace fbc {
-void destroy_batched(Plan* p) { (void)p; }
-std::string batched_describe(const Plan* p) { (void)p; return "batched"; }
+
+struct BVariant {
+    int fh, fw, D, N;
+    Config cfg;
+    int th, two, cb;       // tile geometry: output rows, columns, channels
+    int lds;
+};
+
+struct BatchedState {
+    std::vector<fbcorr_desc> descs;
+    std::vector<BVariant> vars;
+    std::vector<int> img_var;
+    std::vector<int32_t> items;     // 4 ints per item: variant, image, tile, 0
+    std::vector<int32_t> imgs;      // 4 ints per image: H, W, Ho, Wo
+    Kernel kernel, reset;
+    int grid = 0, threads = 256;
+    size_t off_counter = 0, off_items = 0, off_imgs = 0, ws_bytes = 0;
+    int64_t nitems = 0;
+    double flops = 0;
+    std::string source_desc;
+    // uploads and graphs
+    std::set<void*> uploaded;
+    struct GraphKey {
+        hipStream_t s;
+        void* ws;
+        const void *xs, *wts, *ys;
+        bool operator<(const GraphKey& o) const {
+            return std::tie(s, ws, xs, wts, ys) < std::tie(o.s, o.ws, o.xs, o.wts, o.ys);
+        }
+    };
+    std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+};
+
+static int cdiv(int a, int b) { return (a + b - 1) / b; }
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Four waves per workgroup for every variant (one block size for the launch).
+static Config batched_variant_config(int D, int N) {
+    Config c = default_igemm(D, N, false);
+    const int s = c.get("s");
+    const int tiles = std::min(4, std::max(1, cdiv(N * s, 32)));
+    int nt = 1, wn = 1;
+    if (tiles >= 4) { nt = 2; wn = 2; }
+    else if (tiles >= 2) { nt = 2; wn = 1; }
+    const int wm = 4 / wn;
+    c.v["nt"] = nt;
+    c.v["wn"] = wn;
+    c.v["wm"] = wm;
+    c.v["ks"] = 1;
+    c.v["mt"] = 1;
+    c.v["mr"] = 2;
+    c.v["ustage"] = 1;
+    c.v["kc"] = D <= 16 ? D : 16;
+    return c;
+}
+
+static std::vector<std::string> body_macros(const std::string& body) {
+    std::vector<std::string> names;
+    std::istringstream is(body);
+    std::string line;
+    while (std::getline(is, line)) {
+        size_t p = line.find_first_not_of(" \t");
+        if (p == std::string::npos || line.compare(p, 7, "#define") != 0) continue;
+        std::istringstream ls(line.substr(p + 7));
+        std::string name;
+        ls >> name;
+        auto paren = name.find('(');
+        if (paren != std::string::npos) name = name.substr(0, paren);
+        if (!name.empty()) names.push_back(name);
+    }
+    return names;
+}
+
+static bool generate(BatchedState& st, const DeviceInfo& di, KernelSource& ks, std::string& err) {
+    const std::string& tpl = template_source("igemm");
+    const auto b0 = tpl.find("//@@BODY-BEGIN"), b1 = tpl.find("//@@BODY-END");
+    if (b0 == std::string::npos || b1 == std::string::npos) { err = "igemm template lacks body markers"; return false; }
+    const std::string header = tpl.substr(0, b0);
+    const std::string body = tpl.substr(b0, b1 - b0);
+    const std::vector<std::string> macros = body_macros(body);
+    std::ostringstream src;
+    src << "// Generated persistent batched filter-bank correlation: " << st.vars.size() << " variant(s).\n";
+    src << "#define FB_BATCHED 1\n" << header;
+    int maxlds = 16;
+    const char* keys[] = {"kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage"};
+    const char* defs[] = {"FB_KC", "FB_S", "FB_MR", "FB_MT", "FB_NT", "FB_WM", "FB_WN", "FB_KS", "FB_XPAD",
+                          "FB_WPAD", "FB_USTAGE"};
+    for (size_t v = 0; v < st.vars.size(); ++v) {
+        const BVariant& bv = st.vars[v];
+        src << "\n// ---- variant " << v << ": fh=" << bv.fh << " fw=" << bv.fw << " D=" << bv.D << " N=" << bv.N
+            << "  [" << bv.cfg.str() << "]\n";
+        src << "#undef FB_TAG\n#define FB_TAG v" << v << "\n";
+        src << "#define FB_FH " << bv.fh << "\n#define FB_FW " << bv.fw << "\n#define FB_CIN " << bv.D
+            << "\n#define FB_COUT " << bv.N << "\n#define FB_PADH 0\n#define FB_PADW 0\n#define FB_DT 0\n";
+        for (size_t k = 0; k < sizeof(keys) / sizeof(keys[0]); ++k)
+            src << "#define " << defs[k] << " " << bv.cfg.get(keys[k]) << "\n";
+        src << body << "\n";
+        for (auto& m : macros) src << "#undef " << m << "\n";
+        src << "#undef FB_FH\n#undef FB_FW\n#undef FB_CIN\n#undef FB_COUT\n#undef FB_PADH\n#undef FB_PADW\n"
+               "#undef FB_DT\n";
+        for (auto d : defs) src << "#undef " << d << "\n";
+        maxlds = std::max(maxlds, bv.lds);
+    }
+    src << "\n#define MAXLDS " << ((maxlds + 15) / 16 * 16) << "\n";
+    src << R"KSRC(
+// Dispatch: each workgroup takes (variant, image, tile) items from the
+// counter until the table is exhausted; every workgroup then exits.
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_batched(const int4* __restrict__ items, const int nitems, const int4* __restrict__ imgs,
+               const float* const* __restrict__ xs, const float* const* __restrict__ wts,
+               float* const* __restrict__ ys, int* __restrict__ counter)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[MAXLDS];
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = next;
+        __syncthreads();
+        if (it >= nitems) break;
+        const int4 w = items[it];
+        const int4 im = imgs[w.y];
+        const float* x = xs[w.y];
+        const float* wt = wts[w.y];
+        float* y = ys[w.y];
+        switch (w.x) {
+)KSRC";
+    for (size_t v = 0; v < st.vars.size(); ++v) {
+        const BVariant& bv = st.vars[v];
+        src << "        case " << v << ": {\n"
+            << "            const int ntx = (im.w + " << bv.two - 1 << ") / " << bv.two << ";\n"
+            << "            const int nty = (im.z + " << bv.th - 1 << ") / " << bv.th << ";\n"
+            << "            const int tx = w.z % ntx, ty = (w.z / ntx) % nty, cb = w.z / (ntx * nty);\n"
+            << "            igemm_body_v" << v << "(x, wt, nullptr, y, im.x, im.y, im.z, im.w, ty * " << bv.th
+            << ", tx * " << bv.two << ", cb * " << bv.cb << ", lds_raw);\n"
+            << "        } break;\n";
+    }
+    src << R"KSRC(        default: break;
+        }
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(64) fbcorr_batched_reset(int* __restrict__ counter)
+{
+    if (threadIdx.x == 0) *counter = 0;
+}
+)KSRC";
+    ks.name = "fbcorr_batched";
+    ks.file = "batched";
+    ks.source = src.str();
+    ks.options.clear();
+    (void)di;
+    return true;
+}
+
+void destroy_batched(Plan* p) {
+    if (!p->bstate) return;
+    for (auto& g : p->bstate->graphs) {
+        hipGraphExecDestroy(g.second.second);
+        hipGraphDestroy(g.second.first);
+    }
+    delete p->bstate;
+    p->bstate = nullptr;
+}
+
+std::string batched_describe(const Plan* p) {
+    if (!p->bstate) return "batched";
+    std::ostringstream os;
+    os << "batched images=" << p->bstate->descs.size() << " variants=" << p->bstate->vars.size()
+       << " items=" << p->bstate->nitems << " grid=" << p->bstate->grid;
+    for (size_t v = 0; v < p->bstate->vars.size(); ++v) {
+        const BVariant& b = p->bstate->vars[v];
+        os << " | v" << v << " fh=" << b.fh << " fw=" << b.fw << " D=" << b.D << " N=" << b.N << " " << b.cfg.str();
+    }
+    return os.str();
+}
+
+// Plan-time work shared by the device and the offline paths: variants, the
+// work table, the workspace layout and the generated source.
+static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const fbcorr_desc* descs,
+                                     BatchedState* st, KernelSource& ks) {
+    std::map<std::tuple<int, int, int, int>, int> keyidx;
+    for (int32_t i = 0; i < count; ++i) {
+        fbcorr_desc d = descs[i];
+        fbcorr_status s0 = validate_desc(&d);
+        if (s0 != FBCORR_OK) return s0;
+        FBC_RETURN_IF(d.batch != 1, FBCORR_ERR_INVALID_ARGUMENT, "batched descriptors must have batch = 1");
+        FBC_RETURN_IF(d.precision != FBCORR_FP32, FBCORR_ERR_UNSUPPORTED, "batched plans compute in fp32");
+        st->descs.push_back(d);
+        auto key = std::make_tuple(d.fh, d.fw, d.D, d.N);
+        auto it = keyidx.find(key);
+        if (it == keyidx.end()) {
+            BVariant bv{d.fh, d.fw, d.D, d.N, batched_variant_config(d.D, d.N), 0, 0, 0, 0};
+            // shrink until the variant fits the device
+            RoleBuild rb;
+            std::string err;
+            bool ok = false;
+            for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
+                ok = build_role(d, FBCORR_ROLE_FORWARD, bv.cfg, dev, rb, err);
+                if (!ok) {
+                    if (bv.cfg.v["kc"] > 4) bv.cfg.v["kc"] /= 2;
+                    else if (bv.cfg.v["mr"] > 1) bv.cfg.v["mr"] /= 2;
+                    else break;
+                }
+            }
+            FBC_RETURN_IF(!ok, FBCORR_ERR_UNSUPPORTED, "no batched variant fits for key: " + err);
+            const int s = bv.cfg.get("s");
+            bv.th = bv.cfg.get("wm") * bv.cfg.get("mt") * bv.cfg.get("mr");
+            bv.two = s * (32 / bv.cfg.get("mr"));
+            bv.cb = bv.cfg.get("wn") * bv.cfg.get("nt") * 32 / s;
+            bv.lds = rb.main_geom.lds;
+            it = keyidx.emplace(key, (int)st->vars.size()).first;
+            st->vars.push_back(bv);
+        }
+        st->img_var.push_back(it->second);
+    }
+    // work table, largest tiles first (stable: image, then tile order)
+    struct Item { double cost; int v, img, tile; };
+    std::vector<Item> items;
+    for (int32_t i = 0; i < count; ++i) {
+        const fbcorr_desc& d = st->descs[i];
+        const BVariant& bv = st->vars[st->img_var[i]];
+        const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
+        const int nt = cdiv(wo, bv.two) * cdiv(ho, bv.th) * cdiv(d.N, bv.cb);
+        const double cost = (double)bv.th * bv.two * bv.cb * d.fh * d.fw * d.D;
+        for (int t = 0; t < nt; ++t) items.push_back({cost, st->img_var[i], i, t});
+        st->imgs.insert(st->imgs.end(), {d.H, d.W, ho, wo});
+        st->flops += 2.0 * ho * wo * d.N * d.fh * d.fw * d.D;
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    for (auto& it : items) st->items.insert(st->items.end(), {it.v, it.img, it.tile, 0});
+    st->nitems = (int64_t)items.size();
+    FBC_RETURN_IF(st->nitems > 0x7fffffff, FBCORR_ERR_UNSUPPORTED, "too many tiles");
+    // workspace: counter | items | image table
+    st->off_counter = 0;
+    st->off_items = 256;
+    st->off_imgs = st->off_items + align256(st->items.size() * 4);
+    st->ws_bytes = st->off_imgs + align256(st->imgs.size() * 4);
+    std::string err;
+    FBC_RETURN_IF(!generate(*st, dev, ks, err), FBCORR_ERR_INTERNAL, err);
+    return FBCORR_OK;
+}
+
+static fbcorr_status build_batched(Plan* p, int32_t count, const fbcorr_desc* descs) {
+    std::unique_ptr<BatchedState> st(new BatchedState());
+    KernelSource ks;
+    fbcorr_status s = prepare_batched(p->dev, count, descs, st.get(), ks);
+    if (s != FBCORR_OK) return s;
+    s = load_kernel(ks, p->device, st->kernel);
+    if (s != FBCORR_OK) return s;
+    KernelSource rs = ks;
+    rs.name = "fbcorr_batched_reset";
+    s = load_kernel(rs, p->device, st->reset);
+    if (s != FBCORR_OK) return s;
+    int per_cu = 0;
+    hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st->kernel.fn, 256, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    st->grid = (int)std::min<int64_t>(st->nitems, (int64_t)p->dev.cus * per_cu);
+    st->grid = std::max(st->grid, 1);
+    p->batch_ws = st->ws_bytes;
+    p->bstate = st.release();
+    return FBCORR_OK;
+}
+
+static fbcorr_status launch_batched(Plan* p, const float* const* xs, const float* const* wts, float* const* ys,
+                                    void* ws, hipStream_t s) {
+    BatchedState* st = p->bstate;
+    char* base = (char*)ws;
+    int* counter = (int*)(base + st->off_counter);
+    const void* items = base + st->off_items;
+    const void* imgs = base + st->off_imgs;
+    int nitems = (int)st->nitems;
+    void* a0[] = {&counter};
+    fbcorr_status r = launch(st->reset, LaunchGeom{1, 1, 64, 0}, s, a0);
+    if (r != FBCORR_OK) return r;
+    void* a1[] = {(void*)&items, &nitems, (void*)&imgs, (void*)&xs, (void*)&wts, (void*)&ys, &counter};
+    hipEvent_t ev;
+    timing_begin(p, FBCORR_ROLE_FORWARD, s, ev);
+    r = launch(st->kernel, LaunchGeom{st->grid, 1, 256, 0}, s, a1);
+    timing_end(p, FBCORR_ROLE_FORWARD, s, ev);
+    return r;
+}
+
 }  // namespace fbc
 
 using namespace fbc;
 
 extern "C" fbcorr_status fbcorr_plan_batched(int32_t count, const fbcorr_desc* descs, int device, fbcorr_plan_t* out) {
-    (void)count; (void)descs; (void)device; (void)out;
-    set_error(FBCORR_ERR_UNSUPPORTED, "batched plans are not available in this build");
-    return FBCORR_ERR_UNSUPPORTED;
+    try {
+        clear_error();
+        FBC_RETURN_IF(!out || !descs, FBCORR_ERR_INVALID_ARGUMENT, "NULL argument");
+        FBC_RETURN_IF(count <= 0, FBCORR_ERR_INVALID_ARGUMENT, "count must be >= 1");
+        std::unique_ptr<Plan> p(new Plan());
+        p->desc = descs[0];
+        p->device = device;
+        p->batched = true;
+        fbcorr_status st = device_info(device, p->dev);
+        if (st != FBCORR_OK) return st;
+        DeviceGuard g(device);
+        st = build_batched(p.get(), count, descs);
+        if (st != FBCORR_OK) return st;
+        *out = reinterpret_cast<fbcorr_plan_t>(p.release());
+        return FBCORR_OK;
+    } catch (const std::exception& e) {
+        set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what());
+        return FBCORR_ERR_INTERNAL;
+    }
 }
 
 extern "C" fbcorr_status fbcorr_forward_batched(fbcorr_plan_t plan, const float* const* xs, const float* const* ws_,
                                                 float* const* ys, void* workspace, size_t workspace_bytes,
                                                 void* stream, int use_graph) {
-    (void)plan; (void)xs; (void)ws_; (void)ys; (void)workspace; (void)workspace_bytes; (void)stream; (void)use_graph;
-    set_error(FBCORR_ERR_UNSUPPORTED, "batched plans are not available in this build");
-    return FBCORR_ERR_UNSUPPORTED;
+    try {
+        clear_error();
+        Plan* p = reinterpret_cast<Plan*>(plan);
+        FBC_RETURN_IF(!p || !p->batched || !p->bstate, FBCORR_ERR_INVALID_ARGUMENT, "not a batched plan");
+        FBC_RETURN_IF(!xs || !ws_ || !ys, FBCORR_ERR_INVALID_ARGUMENT, "pointer arrays must not be NULL");
+        BatchedState* st = p->bstate;
+        fbcorr_status r = check_ws(workspace, workspace_bytes, st->ws_bytes);
+        if (r != FBCORR_OK) return r;
+        DeviceGuard g(p->device);
+        hipStream_t s = (hipStream_t)stream;
+        if (!st->uploaded.count(workspace)) {
+            // the work table and image table live in the caller's workspace
+            char* base = (char*)workspace;
+            hipError_t e = hipMemcpyAsync(base + st->off_items, st->items.data(), st->items.size() * 4,
+                                          hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(base + st->off_imgs, st->imgs.data(), st->imgs.size() * 4,
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("table upload: ") + hipGetErrorString(e));
+            st->uploaded.insert(workspace);
+        }
+        if (!use_graph) return launch_batched(p, xs, ws_, ys, workspace, s);
+        FBC_RETURN_IF(s == nullptr, FBCORR_ERR_INVALID_ARGUMENT,
+                      "graph capture needs a created stream, not the null stream");
+        BatchedState::GraphKey key{s, workspace, xs, ws_, ys};
+        auto it = st->graphs.find(key);
+        if (it == st->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("begin capture: ") + hipGetErrorString(e));
+            const bool was = p->timing;
+            p->timing = false;             // no event records inside the graph
+            r = launch_batched(p, xs, ws_, ys, workspace, s);
+            p->timing = was;
+            e = hipStreamEndCapture(s, &graph);
+            FBC_RETURN_IF(r != FBCORR_OK, r, fbcorr_last_error());
+            FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("end capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                hipGraphDestroy(graph);
+                set_error(FBCORR_ERR_LAUNCH, std::string("graph instantiate: ") + hipGetErrorString(e));
+                return FBCORR_ERR_LAUNCH;
+            }
+            it = st->graphs.emplace(key, std::make_pair(graph, exec)).first;
+        }
+        hipEvent_t ev;
+        timing_begin(p, FBCORR_ROLE_FORWARD, s, ev);
+        hipError_t e = hipGraphLaunch(it->second.second, s);
+        timing_end(p, FBCORR_ROLE_FORWARD, s, ev);
+        FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("graph launch: ") + hipGetErrorString(e));
+        return FBCORR_OK;
+    } catch (const std::exception& e) {
+        set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what());
+        return FBCORR_ERR_INTERNAL;
+    }
+}
+
+extern "C" fbcorr_status fbcorr_compile_check_batched(int32_t count, const fbcorr_desc* descs, const char* arch,
+                                                     size_t* code_bytes) {
+    try {
+        clear_error();
+        FBC_RETURN_IF(!descs || count <= 0, FBCORR_ERR_INVALID_ARGUMENT, "need at least one descriptor");
+        DeviceInfo di;
+        di.arch = arch ? arch : "gfx950";
+        di.cus = 256;
+        di.lds_per_block = 160 * 1024;
+        di.max_threads = 1024;
+        BatchedState st;
+        KernelSource ks;
+        fbcorr_status s = prepare_batched(di, count, descs, &st, ks);
+        if (s != FBCORR_OK) return s;
+        std::shared_ptr<const std::vector<char>> code;
+        s = compile_cached(ks, di.arch, code);
+        if (s != FBCORR_OK) return s;
+        if (code_bytes) *code_bytes = code->size();
+        return FBCORR_OK;
+    } catch (const std::exception& e) {
+        set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what());
+        return FBCORR_ERR_INTERNAL;
+    }
 }

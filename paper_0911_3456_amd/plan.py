@@ -201,3 +201,86 @@ def fbcorr(x: torch.Tensor, w: torch.Tensor, precision: str = "fp32", algo: str 
     plan = get_plan(B, H, W, D, N, fh, fw, precision, algo, device=x.device)
     y = FbCorrFunction.apply(x.contiguous(), w.contiguous(), plan)
     return y[0] if squeeze else y
+
+
+class BatchedPlan:
+    """Many independent problems (each its own image and filter bank) in one
+    persistent launch, optionally replayed from a captured HIP graph."""
+
+    def __init__(self, shapes, device=None):
+        """shapes: sequence of (H, W, D, N, fh, fw)."""
+        self.lib = nat.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        descs = [nat.make_desc(1, *s) for s in self.shapes]
+        arr = (nat.Desc * len(descs))(*descs)
+        h = ctypes.c_void_p()
+        nat.check(self.lib.fbcorr_plan_batched(len(descs), arr, self.device.index, ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_size_t()
+        nat.check(self.lib.fbcorr_workspace_size(h, 0, ctypes.byref(n)))
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws[off:off + n.value]
+        # device arrays of pointers; their addresses stay fixed for graph replay
+        k = len(self.shapes)
+        self.px = torch.zeros(k, dtype=torch.int64, device=self.device)
+        self.pw = torch.zeros(k, dtype=torch.int64, device=self.device)
+        self.py = torch.zeros(k, dtype=torch.int64, device=self.device)
+
+    @property
+    def flops(self) -> int:
+        return sum(2 * (H - fh + 1) * (W - fw + 1) * N * fh * fw * D for H, W, D, N, fh, fw in self.shapes)
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1 << 16)
+        nat.check(self.lib.fbcorr_plan_get_config(self.handle, 0, buf, 1 << 16))
+        return buf.value.decode()
+
+    def output_buffers(self):
+        return [torch.empty((H - fh + 1, W - fw + 1, N), dtype=torch.float32, device=self.device)
+                for H, W, D, N, fh, fw in self.shapes]
+
+    def set_pointers(self, xs, ws, ys) -> None:
+        for i, (H, W, D, N, fh, fw) in enumerate(self.shapes):
+            _check_tensor(xs[i], (H, W, D), "xs[%d]" % i)
+            _check_tensor(ws[i], (N, fh, fw, D), "ws[%d]" % i)
+            _check_tensor(ys[i], (H - fh + 1, W - fw + 1, N), "ys[%d]" % i)
+        ptrs = torch.tensor([[t.data_ptr() for t in xs], [t.data_ptr() for t in ws],
+                             [t.data_ptr() for t in ys]], dtype=torch.int64)
+        self.px.copy_(ptrs[0])
+        self.pw.copy_(ptrs[1])
+        self.py.copy_(ptrs[2])
+
+    def forward(self, xs, ws, ys=None, use_graph=False):
+        ys = self.output_buffers() if ys is None else ys
+        self.set_pointers(xs, ws, ys)
+        self.launch(use_graph)
+        return ys
+
+    def launch(self, use_graph=False) -> None:
+        """Run with the pointers last set (a graph replays them as they are)."""
+        nat.check(self.lib.fbcorr_forward_batched(
+            self.handle, _ptr(self.px), _ptr(self.pw), _ptr(self.py), _ptr(self.ws), self.ws.numel(),
+            ctypes.c_void_p(_stream_handle(self.device)), 1 if use_graph else 0))
+
+    def enable_timing(self, on=True) -> None:
+        nat.check(self.lib.fbcorr_plan_enable_timing(self.handle, 1 if on else 0))
+
+    def read_timing(self, reset=True):
+        ms = (ctypes.c_double * 3)()
+        calls = (ctypes.c_int64 * 3)()
+        nat.check(self.lib.fbcorr_plan_read_timing(self.handle, ms, calls, 1 if reset else 0))
+        return ms[0], calls[0]
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.lib.fbcorr_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
