@@ -17,6 +17,8 @@ Also printed in the same JSON line:
   precision     the 512x512x16 / 128x13x13x16 forward: fp32 direct,
                 fp32 matrix-core, bf16 and fp16 matrix-core times and the
                 bf16/fp16 speedups (error bounds are enforced by the tests).
+  batched       256 uneven images with their own banks in one persistent
+                launch, replayed from a HIP graph.
 """
 from __future__ import annotations
 
@@ -44,6 +46,7 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="run the tuner for every role first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only", choices=["step", "forward", "backward_x", "backward_w"], default="step",
                     help="profiling aid: time one role only")
     return ap.parse_args()
@@ -133,6 +136,47 @@ def precision_leg(steps: int, warmup: int):
         out[k]["speedup_vs_fp32_direct"] = round(base / out[k]["ms"], 3)
     out["workload"] = "512x512x16 input, 128 filters 13x13x16 (forward only)"
     out["bf16_frac_of_peak"] = round(out["bf16_igemm"]["tflops"] / BF16_MATRIX_PEAK_TFLOPS, 4)
+    return out
+
+
+def batched_leg(steps: int, warmup: int):
+    """256 uneven images (own bank each) in one persistent launch replayed
+    from a HIP graph: throughput over the whole batch."""
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import BatchedPlan
+    shapes, xs, fs = wl.draw_batched()
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    plan = BatchedPlan([(s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes], device=dev)
+    plan_s = time.perf_counter() - t0
+    xd = [torch.from_numpy(a).to(dev) for a in xs]
+    fd = [torch.from_numpy(a).to(dev) for a in fs]
+    ys = plan.output_buffers()
+    plan.set_pointers(xd, fd, ys)
+    side = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for _ in range(max(1, warmup // 2)):
+            plan.launch(use_graph=True)
+        side.synchronize()
+        plan.enable_timing(True)
+        reps = max(3, steps // 10)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.launch(use_graph=True)
+        side.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        plan.enable_timing(False)
+    ms, calls = plan.read_timing()
+    desc = plan.describe()
+    nvar = int(desc.split("variants=")[1].split()[0])
+    out = {"workload": "256 images, sides 96..512, D 4..32, N 16..128, f 3..11, own bank each (forward)",
+           "gflop": round(plan.flops / 1e9, 2), "ms": round(sec * 1e3, 3),
+           "graph_launch_ms": round(ms / max(calls, 1), 3),
+           "tflops": round(plan.flops / sec / 1e12, 2), "variants": nvar,
+           "plan_s": round(plan_s, 2)}
+    plan.close()
     return out
 
 
@@ -230,6 +274,9 @@ def main():
     if not args.no_precision and args.only == "step":
         log("precision leg ...")
         result["precision"] = precision_leg(args.steps, args.warmup)
+    if not args.no_batched and args.only == "step":
+        log("batched leg ...")
+        result["batched"] = batched_leg(args.steps, args.warmup)
     if not args.no_cpu_baseline and args.only == "step":
         log("cpu baseline (FP64 oracle) ...")
         result["cpu_baseline"] = cpu_baseline(s, x, w, g)

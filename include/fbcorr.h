@@ -231,8 +231,17 @@ FBCORR_API fbcorr_status fbcorr_compile_check(const fbcorr_desc* desc, int role,
 FBCORR_API fbcorr_status fbcorr_compile_check_batched(int32_t count, const fbcorr_desc* descs, const char* arch,
                                                       size_t* code_bytes);
 
-/* In-process code-object cache statistics (hits, misses, entries). */
-FBCORR_API fbcorr_status fbcorr_cache_stats(int64_t* hits, int64_t* misses, int64_t* entries);
+/* Code-object cache statistics: in-memory hits, compilations (misses),
+ * in-memory entries, and entries read from the on-disk cache.  The on-disk
+ * cache (Fig. 2: compiled code is kept across runs and reused while source
+ * and environment are unchanged) lives in $FBCORR_CACHE_DIR, else in
+ * _rtc_cache/ beside the library; FBCORR_CACHE=0 disables it.  Entries are
+ * checksummed; a damaged entry is recompiled and rewritten. */
+FBCORR_API fbcorr_status fbcorr_cache_stats(int64_t* hits, int64_t* misses, int64_t* entries, int64_t* disk_hits);
+
+/* Drop the in-memory code-object cache (loaded modules stay valid) and
+ * re-read the tuning database on next use. */
+FBCORR_API fbcorr_status fbcorr_cache_clear(void);
 
 FBCORR_API const char* fbcorr_last_error(void);              /* thread-local; valid until the next call */
 FBCORR_API const char* fbcorr_status_string(fbcorr_status s);

@@ -9,8 +9,8 @@ The computation lives in ``libfbcorr.so`` (C ABI in ``include/fbcorr.h``);
 this package only marshals torch tensors and streams into it.
 """
 from . import _native
-from ._native import FbcorrError, codegen, compile_check, compile_check_batched, cache_stats, make_desc, load
+from ._native import FbcorrError, codegen, compile_check, compile_check_batched, cache_stats, cache_clear, make_desc, load
 from .plan import BatchedPlan, FbCorrFunction, Plan, fbcorr, get_plan
 
 __all__ = ["BatchedPlan", "FbcorrError", "FbCorrFunction", "Plan", "fbcorr", "get_plan", "codegen",
-           "compile_check", "compile_check_batched", "cache_stats", "make_desc", "load"]
+           "compile_check", "compile_check_batched", "cache_stats", "cache_clear", "make_desc", "load"]

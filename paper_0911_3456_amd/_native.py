@@ -32,7 +32,7 @@ EXPORTS = (
     "fbcorr_backward", "fbcorr_tune", "fbcorr_plan_batched", "fbcorr_forward_batched",
     "fbcorr_plan_get_config", "fbcorr_plan_set_config", "fbcorr_plan_enable_timing",
     "fbcorr_plan_read_timing", "fbcorr_codegen", "fbcorr_compile_check", "fbcorr_compile_check_batched",
-    "fbcorr_cache_stats",
+    "fbcorr_cache_stats", "fbcorr_cache_clear",
     "fbcorr_last_error", "fbcorr_status_string", "fbcorr_version",
 )
 
@@ -102,7 +102,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.c_char_p, ctypes.POINTER(sz)]
     lib.fbcorr_compile_check_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), ctypes.c_char_p,
                                                  ctypes.POINTER(sz)]
-    lib.fbcorr_cache_stats.argtypes = [ctypes.POINTER(ctypes.c_int64)] * 3
+    lib.fbcorr_cache_stats.argtypes = [ctypes.POINTER(ctypes.c_int64)] * 4
+    lib.fbcorr_cache_clear.argtypes = []
     lib.fbcorr_last_error.restype = ctypes.c_char_p
     lib.fbcorr_last_error.argtypes = []
     lib.fbcorr_status_string.restype = ctypes.c_char_p
@@ -157,6 +158,10 @@ def compile_check_batched(descs, arch: str = "gfx950") -> int:
 
 def cache_stats():
     lib = load()
-    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    check(lib.fbcorr_cache_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return {"hits": a.value, "misses": b.value, "entries": c.value}
+    a, b, c, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib.fbcorr_cache_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+    return {"hits": a.value, "misses": b.value, "entries": c.value, "disk_hits": d.value}
+
+
+def cache_clear() -> None:
+    check(load().fbcorr_cache_clear())

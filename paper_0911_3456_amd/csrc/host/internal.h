@@ -69,7 +69,9 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
 // Load (cached per device + key) and fetch the function.
 fbcorr_status load_kernel(const KernelSource& ks, int device, Kernel& out);
 std::string hiprtc_version_string();
-void cache_stats(int64_t& hits, int64_t& misses, int64_t& entries);
+void cache_stats(int64_t& hits, int64_t& misses, int64_t& entries, int64_t& disk_hits);
+void cache_clear_memory();
+std::string disk_cache_dir();
 
 // Device facts used for validation and launch shapes.
 struct DeviceInfo {

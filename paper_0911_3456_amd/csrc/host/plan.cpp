@@ -472,14 +472,24 @@ fbcorr_status fbcorr_compile_check(const fbcorr_desc* desc, int role, const char
     FBC_API_END
 }
 
-fbcorr_status fbcorr_cache_stats(int64_t* hits, int64_t* misses, int64_t* entries) {
+fbcorr_status fbcorr_cache_stats(int64_t* hits, int64_t* misses, int64_t* entries, int64_t* disk_hits) {
     FBC_API_BEGIN
     clear_error();
-    int64_t h, m, e;
-    cache_stats(h, m, e);
+    int64_t h, m, e, d;
+    cache_stats(h, m, e, d);
     if (hits) *hits = h;
     if (misses) *misses = m;
     if (entries) *entries = e;
+    if (disk_hits) *disk_hits = d;
+    return FBCORR_OK;
+    FBC_API_END
+}
+
+fbcorr_status fbcorr_cache_clear(void) {
+    FBC_API_BEGIN
+    clear_error();
+    cache_clear_memory();
+    tuning_db_reload();
     return FBCORR_OK;
     FBC_API_END
 }

@@ -8,7 +8,13 @@
 // hiprtc version; the cache lives for the process.
 #include "internal.h"
 
+#include <dlfcn.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <sstream>
 #include <unordered_map>
 
@@ -54,7 +60,7 @@ std::string hiprtc_version_string() {
 namespace {
 std::mutex g_cache_mu;
 std::unordered_map<std::string, std::shared_ptr<const std::vector<char>>> g_code;
-int64_t g_hits = 0, g_misses = 0;
+int64_t g_hits = 0, g_misses = 0, g_disk_hits = 0;
 
 struct LoadedKey {
     int device;
@@ -80,6 +86,60 @@ static std::string cache_key(const KernelSource& ks, const std::string& arch) {
     return ks.name + "-" + buf;
 }
 
+// Semi-permanent on-disk cache (Fig. 2: compiled code survives the process
+// and is reused while source and environment are unchanged).  The file name
+// is the cache key, which already hashes the source, the options, the
+// architecture and the compiler version.  Entries carry a checksum; a
+// damaged entry is ignored and rewritten.
+std::string disk_cache_dir() {
+    const char* off = getenv("FBCORR_CACHE");
+    if (off && std::string(off) == "0") return "";
+    const char* env = getenv("FBCORR_CACHE_DIR");
+    if (env && *env) return env;
+    Dl_info info;
+    if (dladdr((void*)&disk_cache_dir, &info) && info.dli_fname) {
+        std::string so = info.dli_fname;
+        auto slash = so.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/_rtc_cache";
+    }
+    return "";
+}
+
+static const char kMagic[8] = {'F', 'B', 'C', 'C', 'O', 'D', 'E', '1'};
+
+static bool disk_load(const std::string& key, std::vector<char>& code) {
+    const std::string dir = disk_cache_dir();
+    if (dir.empty()) return false;
+    std::ifstream in(dir + "/" + key + ".co", std::ios::binary);
+    if (!in) return false;
+    char magic[8];
+    uint64_t size = 0, sum = 0;
+    if (!in.read(magic, 8) || memcmp(magic, kMagic, 8) != 0) return false;
+    if (!in.read((char*)&size, 8) || !in.read((char*)&sum, 8) || size == 0 || size > (1ull << 30)) return false;
+    code.resize(size);
+    if (!in.read(code.data(), (std::streamsize)size)) return false;
+    return fnv1a(std::string(code.data(), code.size())) == sum;
+}
+
+static void disk_store(const std::string& key, const std::vector<char>& code) {
+    const std::string dir = disk_cache_dir();
+    if (dir.empty()) return;
+    mkdir(dir.c_str(), 0755);
+    const std::string path = dir + "/" + key + ".co";
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    {
+        std::ofstream out(tmp, std::ios::binary);
+        if (!out) return;
+        const uint64_t size = code.size(), sum = fnv1a(std::string(code.data(), code.size()));
+        out.write(kMagic, 8);
+        out.write((const char*)&size, 8);
+        out.write((const char*)&sum, 8);
+        out.write(code.data(), (std::streamsize)size);
+        if (!out) { out.close(); unlink(tmp.c_str()); return; }
+    }
+    if (rename(tmp.c_str(), path.c_str()) != 0) unlink(tmp.c_str());
+}
+
 static bool supported_arch(const std::string& a) {
     // The kernels use CDNA3/CDNA4 matrix instructions; gfx950 is the target.
     return a == "gfx950";
@@ -93,6 +153,19 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_code.find(key);
         if (it != g_code.end()) { ++g_hits; code = it->second; return FBCORR_OK; }
+    }
+    {
+        auto buf = std::make_shared<std::vector<char>>();
+        if (disk_load(key, *buf)) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            ++g_disk_hits;
+            g_code[key] = buf;
+            code = buf;
+            return FBCORR_OK;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
         ++g_misses;
     }
     hiprtcProgram prog;
@@ -124,6 +197,7 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
     auto buf = std::make_shared<std::vector<char>>(cs);
     hiprtcGetCode(prog, buf->data());
     hiprtcDestroyProgram(&prog);
+    disk_store(key, *buf);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         g_code[key] = buf;
@@ -132,9 +206,14 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
     return FBCORR_OK;
 }
 
-void cache_stats(int64_t& hits, int64_t& misses, int64_t& entries) {
+void cache_stats(int64_t& hits, int64_t& misses, int64_t& entries, int64_t& disk_hits) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
-    hits = g_hits; misses = g_misses; entries = (int64_t)g_code.size();
+    hits = g_hits; misses = g_misses; entries = (int64_t)g_code.size(); disk_hits = g_disk_hits;
+}
+
+void cache_clear_memory() {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_code.clear();
 }
 
 fbcorr_status device_info(int device, DeviceInfo& out) {

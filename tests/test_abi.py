@@ -163,3 +163,64 @@ def test_gpu_test_configurations_are_valid():
         fb.codegen(d, "backward_x", "algo=igemm " + c)
     for c in tb.BW_CFGS:
         fb.codegen(d, "backward_w", "algo=dw " + c)
+
+
+def test_disk_cache_reuse_and_corruption(tmp_path, monkeypatch):
+    """Compiled code persists on disk keyed by source, options, architecture
+    and compiler version; a damaged entry is recompiled and rewritten."""
+    from paper_0911_3456_amd import cache_clear, cache_stats, compile_check, make_desc
+    monkeypatch.setenv("FBCORR_CACHE_DIR", str(tmp_path))
+    d = make_desc(1, 23, 29, 4, 8, 3, 5)
+    cache_clear()
+    s0 = cache_stats()
+    compile_check(d)
+    s1 = cache_stats()
+    files = sorted(tmp_path.glob("*.co"))
+    assert len(files) >= 1 and s1["misses"] > s0["misses"]
+    cache_clear()
+    compile_check(d)
+    s2 = cache_stats()
+    assert s2["disk_hits"] > s1["disk_hits"] and s2["misses"] == s1["misses"]
+    # damage every entry: it must be recompiled, not loaded
+    for f in files:
+        raw = bytearray(f.read_bytes())
+        raw[-1] ^= 0xFF
+        f.write_bytes(bytes(raw))
+    cache_clear()
+    compile_check(d)
+    s3 = cache_stats()
+    assert s3["misses"] > s2["misses"]
+    cache_clear()
+    compile_check(d)
+    assert cache_stats()["disk_hits"] > s3["disk_hits"]     # rewritten and valid again
+    monkeypatch.setenv("FBCORR_CACHE", "0")
+    cache_clear()
+    s5 = cache_stats()
+    compile_check(d)
+    assert cache_stats()["disk_hits"] == s5["disk_hits"]
+
+
+def test_tuning_database_supplies_defaults(tmp_path, monkeypatch):
+    from paper_0911_3456_amd import cache_clear, codegen, make_desc
+    db = tmp_path / "db.txt"
+    db.write_text("# test\ngfx950 forward fp32 1 40 50 8 64 5 5 : algo=igemm kc=4 mr=2 nt=1 wm=2 wn=2\n")
+    monkeypatch.setenv("FBCORR_TUNING_DB", str(db))
+    cache_clear()
+    _, opts = codegen(make_desc(1, 40, 50, 8, 64, 5, 5))
+    assert "-DFB_KC=4" in opts and "-DFB_MR=2" in opts and "-DFB_WN=2" in opts
+    _, opts2 = codegen(make_desc(1, 40, 51, 8, 64, 5, 5))      # other shape: heuristic
+    assert "-DFB_WN=2" not in opts2
+    db.write_text("gfx950 forward fp32 1 40 50 8 64 5 5 : algo=igemm s=3\n")   # invalid entry
+    cache_clear()
+    _, opts3 = codegen(make_desc(1, 40, 50, 8, 64, 5, 5))
+    assert "-DFB_S=1" in opts3
+    monkeypatch.delenv("FBCORR_TUNING_DB")
+    cache_clear()
+
+
+def test_batched_kernel_generation_compiles():
+    from paper_0911_3456_amd import compile_check_batched, make_desc
+    import workloads as wl
+    shapes, _ = wl.draw_batched_list(count=6, seed=9)
+    descs = [make_desc(1, s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes]
+    assert compile_check_batched(descs) > 0
