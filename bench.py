@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the kernels for a rocprofv3 counter pass and exit")
     ap.add_argument("--only", choices=["step", "forward", "backward_x", "backward_w"], default="step",
                     help="profiling aid: time one role only")
     return ap.parse_args()
@@ -64,19 +66,49 @@ def kernel_fingerprint(plan, role: str) -> str:
     return hashlib.sha256((src + "\0" + opts).encode()).hexdigest()[:16]
 
 
-def load_traffic(role: str, fingerprint: str, launches_bytes: float):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on exactly this kernel (same generated source and options)."""
-    path = os.path.join(ROOT, "profiles", "traffic_fp32_%s.json" % role)
+def load_traffic(role: str, fingerprint: str):
+    """HBM bytes per launch (fetch + write) from the committed rocprofv3
+    counter summary, if it was taken on exactly this kernel (same generated
+    source and options); None otherwise."""
+    path = os.path.join(ROOT, "profiles", "traffic_fp32_256x256x8_64x9x9x8.txt")
     if not os.path.exists(path):
         return None
-    try:
-        rec = json.load(open(path))
-    except ValueError:
-        return None
-    if rec.get("fingerprint") != fingerprint:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    for line in open(path):
+        f = line.split("#")[0].split()
+        if len(f) == 4 and f[0] == role and f[1] == fingerprint:
+            return int(f[2]) + int(f[3])
+    return None
+
+
+COPY_BYTES = 256 << 20
+
+
+def traffic_probe():
+    """For counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE): the fp32
+    workload's kernels three times each, plus a device copy of COPY_BYTES
+    whose counter readings calibrate the counters (it moves COPY_BYTES in
+    and COPY_BYTES out)."""
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import Plan
+    wk = wl.WORKLOADS["fp32"]
+    s = wk.shape
+    x, w, rng = wl.draw_single(s, wk.seed)
+    g = wl.draw_grad(s, rng)
+    dev = torch.device("cuda", 0)
+    xt, wt, gt = (torch.from_numpy(a).to(dev) for a in (x, w, g))
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, device=dev)
+    y = torch.empty(plan.y_shape, device=dev)
+    dx, dw = torch.empty_like(xt), torch.empty_like(wt)
+    a = torch.ones(COPY_BYTES // 4, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        plan.forward(xt, wt, y)
+        plan.backward(xt, wt, gt, dx=dx, dw=dw)
+        b.copy_(a)
+    torch.cuda.synchronize()
+    for r in ROLES:
+        print(r, kernel_fingerprint(plan, r), plan.get_config(r), flush=True)
 
 
 def time_steps(fn, steps: int, warmup: int):
@@ -182,6 +214,9 @@ def batched_leg(steps: int, warmup: int):
 
 def main():
     args = parse()
+    if args.traffic_probe:
+        traffic_probe()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
@@ -242,7 +277,7 @@ def main():
     dom = max(kern, key=kern.get)
     achieved = s.flops / (kern[dom] * 1e-3) / 1e12
     fp = kernel_fingerprint(plan, dom)
-    traffic = load_traffic(dom, fp, None)
+    traffic = load_traffic(dom, fp)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_MATRIX_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_MATRIX_PEAK_TFLOPS, 4),
                 "traffic": traffic, "kernel": dom, "kernel_ms": round(kern[dom], 5),
