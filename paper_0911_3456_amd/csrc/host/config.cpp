@@ -107,8 +107,10 @@ static std::vector<Config> shrink_sequence(const Config& base) {
             if (c.v["th"] > 1) c.v["th"] /= 2;
             else break;
         } else {
-            if (c.v["rh"] > 1) c.v["rh"] /= 2;
+            if (c.v["pf"]) c.v["pf"] = 0;
+            else if (c.v["rh"] > 1) c.v["rh"] /= 2;
             else if (c.v["rw"] > 8) c.v["rw"] /= 2;
+            else if (c.v["nw"] < 16) c.v["nw"] *= 2;
             else break;
         }
         out.push_back(c);
@@ -129,13 +131,19 @@ Config default_direct(const fbcorr_desc& d) {
     return c;
 }
 
+static int dw_tiles(const fbcorr_desc& d) {
+    return cdiv(d.N, 32) * cdiv(d.fh * d.fw * d.D, 32);
+}
+
 Config default_dw(const fbcorr_desc& d, int cus) {
     Config c;
     c.algo = "dw";
-    int wm = d.N <= 32 ? 1 : (d.N <= 64 ? 2 : 4);
-    int wn = std::max(1, 8 / wm);
-    c.v = {{"rh", 4}, {"rw", 32}, {"mt", 1}, {"nt", 3}, {"wm", wm}, {"wn", wn}, {"gpad", 4}, {"xpad", 4}, {"np", 0}};
-    (void)cus;
+    const int tiles = dw_tiles(d);
+    const int tpb = cdiv(tiles, 2);
+    const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
+    const long nchunks = (long)d.batch * cdiv(ho, 2) * cdiv(wo, 32);
+    const int np = (int)std::max<long>(1, std::min<long>(nchunks, std::max(1, cus) / 2));
+    c.v = {{"rh", 2}, {"rw", 32}, {"nw", 8}, {"tpb", tpb}, {"np", np}, {"gpad", 4}, {"xpad", 4}, {"pf", 1}};
     return c;
 }
 
@@ -270,33 +278,30 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
 
 static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di, LaunchGeom& g,
                     KernelSource& ks, int& np_out, std::string& err) {
-    const int rh = c.get("rh"), rw = c.get("rw"), mt = c.get("mt"), nt = c.get("nt");
-    const int wm = c.get("wm"), wn = c.get("wn"), gpad = c.get("gpad"), xpad = c.get("xpad");
+    const int rh = c.get("rh"), rw = c.get("rw"), nw = c.get("nw"), tpb = c.get("tpb");
+    const int gpad = c.get("gpad"), xpad = c.get("xpad"), pf = c.get("pf");
     int np = c.get("np");
-    if (rh < 1 || rw < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || gpad < 0 || xpad < 0 || np < 0) {
+    if (rh < 1 || rw < 1 || nw < 1 || tpb < 1 || gpad < 0 || xpad < 0 || np < 1) {
         err = "dw: every knob must be positive"; return false;
     }
     if ((rh * rw) % 2) { err = "dw: rh*rw must be even"; return false; }
-    if (mt * nt > 8) { err = "dw: more than 8 accumulator tiles per wave"; return false; }
-    const int threads = wm * wn * 64;
+    const int tiles = dw_tiles(d);
+    const int tpb_eff = std::min(tpb, tiles);
+    if (cdiv(tpb_eff, nw) > 8) { err = "dw: more than 8 accumulator tiles per wave"; return false; }
+    const int threads = nw * 64;
     if (threads > std::min(1024, di.max_threads)) { err = "dw: too many threads"; return false; }
     const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
-    const int qtot = d.fh * d.fw * d.D;
-    const int rb = wm * mt * 32, cbk = wn * nt * 32;
+    const int npad = cdiv(d.N, 32) * 32;
     const int pc = rh * rw;
-    const long lds = ((long)pc * (rb + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
+    const long lds = ((long)pc * (npad + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
     if (lds > di.lds_per_block) { err = "dw: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
+    const long prefetch_regs = pf ? (cdivl((long)pc * npad, threads) + cdivl((long)(rh + d.fh - 1) * (rw + d.fw - 1) * d.D, threads)) : 0;
+    if (prefetch_regs > 96) { err = "dw: prefetch needs too many registers"; return false; }
     const long nchunks = (long)d.batch * cdiv(ho, rh) * cdiv(wo, rw);
-    const int gy = cdiv(d.N, rb) * cdiv(qtot, cbk);
-    if (np == 0) {
-        // enough workgroups for about two per compute unit, at most one per chunk
-        long want = cdivl(2L * std::max(di.cus, 1), gy);
-        np = (int)std::min<long>(std::max<long>(want, 1), nchunks);
-    }
     if (np > nchunks) np = (int)nchunks;
-    if (np < 1 || np > 65535) { err = "dw: partial count out of range"; return false; }
+    if (np > 65535) { err = "dw: partial count out of range"; return false; }
     g.grid_x = np;
-    g.grid_y = gy;
+    g.grid_y = cdiv(tiles, tpb_eff);
     g.threads = threads;
     g.lds = (int)lds;
     np_out = np;
@@ -307,8 +312,9 @@ static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di,
     opt(ks.options, "BATCH", d.batch); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw);
     opt(ks.options, "D", d.D); opt(ks.options, "N", d.N); opt(ks.options, "H", d.H); opt(ks.options, "W", d.W);
     opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
-    opt(ks.options, "RH", rh); opt(ks.options, "RW", rw); opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
-    opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "GPAD", gpad); opt(ks.options, "XPAD", xpad);
+    opt(ks.options, "RH", rh); opt(ks.options, "RW", rw); opt(ks.options, "NW", nw); opt(ks.options, "TPB", tpb_eff);
+    opt(ks.options, "NP", np); opt(ks.options, "GPAD", gpad); opt(ks.options, "XPAD", xpad);
+    opt(ks.options, "PF", pf ? 1 : 0);
     return true;
 }
 
@@ -338,7 +344,7 @@ static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
         {"igemm", {"kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd"}},
-        {"dw", {"rh", "rw", "mt", "nt", "wm", "wn", "gpad", "xpad", "np"}},
+        {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }

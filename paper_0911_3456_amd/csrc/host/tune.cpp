@@ -125,18 +125,27 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         }
     } else {
         const Config base = default_config(d, role, DeviceInfo{"gfx950", 256, 160 * 1024, 1024});
-        const int shapes[][4] = {{1, 3, 2, 4}, {1, 2, 2, 4}, {2, 3, 1, 4}, {1, 4, 2, 2}, {2, 2, 1, 8},
-                                 {1, 3, 2, 2}, {2, 4, 1, 4}, {1, 1, 2, 8}};
-        for (auto& sh : shapes)
-            for (int rh : {2, 4, 8})
-                for (int np : {0, 128, 256, 512}) {
-                    Config c = base;
-                    c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
-                    if (sh[0] * sh[2] * 32 > std::max(32, ((d.N + 31) / 32) * 32)) continue;
-                    c.v["rh"] = rh;
-                    c.v["np"] = np;
-                    add(out, seen, c);
-                }
+        const int tiles = ((d.N + 31) / 32) * ((d.fh * d.fw * d.D + 31) / 32);
+        std::vector<Config> grid;
+        for (int rh : {1, 2, 4})
+            for (int rw : {32, 64})
+                for (int nw : {2, 4, 8})
+                    for (int split : {1, 2, 3, 4, 6})
+                        for (int np : {32, 64, 128, 256})
+                            for (int pf : {0, 1}) {
+                                Config c = base;
+                                c.v["rh"] = rh; c.v["rw"] = rw; c.v["nw"] = nw;
+                                c.v["tpb"] = (tiles + split - 1) / split;
+                                c.v["np"] = np; c.v["pf"] = pf;
+                                grid.push_back(c);
+                            }
+        uint64_t st = 0x2545F4914F6CDD1Dull;
+        for (size_t i = grid.size(); i > 1; --i) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            std::swap(grid[i - 1], grid[(st >> 33) % i]);
+        }
+        add(out, seen, base);
+        for (auto& c : grid) add(out, seen, c);
     }
     return out;
 }

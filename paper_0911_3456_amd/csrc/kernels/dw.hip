@@ -3,18 +3,24 @@
 //   dw[n,u,v,d] = sum_b sum_{i<HO, j<WO} dy[b,i,j,n] * x[b,i+u,j+v,d]
 //
 // GEMM view: rows = filters n, columns = taps q = (u, v, d), contraction over
-// output pixels (b, i, j).  Pixels are cut into chunks of RH x RW output
-// positions; workgroup g takes chunks g, g + P, g + 2P, ... (P = gridDim.x)
-// and writes its partial sums to part[g][n][q] (the caller's workspace).  A
-// separate kernel adds the P partials in a fixed order, so the result does
-// not depend on scheduling.  Per chunk, dy[chunk][n] and the matching input
-// tile with its (FH-1, FW-1) halo are staged in LDS; the B fragment of a lane
-// for column q is the input value at its pixel offset by (u, v), channel d.
+// output pixels (b, i, j).  The 32x32 output tiles of the (n, q) plane are
+// numbered row-fastest; workgroup row blockIdx.y owns TPB consecutive tiles
+// and its NW waves take them round-robin (so no wave computes whole padding
+// tiles).  Pixels are cut into chunks of RH x RW output positions; workgroup
+// column g takes chunks g, g + NP, g + 2NP, ... and writes its partial sums to
+// part[g][n][q] (the caller's workspace); a separate kernel adds the NP
+// partials in a fixed order, so the result does not depend on scheduling.
+// Per chunk, dy[chunk][all n] and the matching input tile with its
+// (FH-1, FW-1) halo are staged in LDS; with PF the next chunk is fetched into
+// registers while the current one is consumed (pre-fetching and software
+// pipelining).  The B fragment of a lane for tap column q is the input value
+// at its pixel offset by (u, v), channel d.
 //
-// Compile-time constants:
+// Compile-time constants (FB_<name>):
 //   problem  BATCH FH FW D N H W HO WO
-//   tiling   RH RW (pixel chunk)  MT NT (32x32 tiles per wave)  WM WN
-//            (waves along rows/cols)  GPAD XPAD (LDS padding)
+//   tiling   RH RW (pixel chunk)  NW (waves)  TPB (tiles per workgroup)
+//            NP (partials = workgroup columns)  GPAD XPAD (LDS padding)
+//            PF (register prefetch of the next chunk)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -34,29 +40,34 @@
 #define WO FB_WO
 #define RH FB_RH
 #define RW FB_RW
-#define MT FB_MT
-#define NT FB_NT
-#define WM FB_WM
-#define WN FB_WN
+#define NW FB_NW
+#define TPB FB_TPB
+#define NP FB_NP
 #define GPAD FB_GPAD
 #define XPAD FB_XPAD
+#define PF FB_PF
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-#define NWAVES (WM * WN)
-#define NTHREADS (NWAVES * 64)
+#define NTHREADS (NW * 64)
 #define QTOT (FH * FW * D)
-#define RB (WM * MT * 32)         // filter rows per workgroup
-#define CBK (WN * NT * 32)        // tap columns per workgroup
-#define PC (RH * RW)              // pixels per chunk
+#define NROWT ((N + 31) / 32)
+#define NCOLT ((QTOT + 31) / 32)
+#define TILES (NROWT * NCOLT)
+#define TPW ((TPB + NW - 1) / NW)        // tiles per wave (at most)
+#define NPAD (NROWT * 32)
+#define GST (NPAD + GPAD)                // dy tile pixel stride
+#define PC (RH * RW)                     // pixels per chunk
 #define XR (RH + FH - 1)
 #define XC (RW + FW - 1)
-#define XRS (XC * D + XPAD)       // input tile row stride
-#define GST (RB + GPAD)           // dy tile pixel stride
+#define XRS (XC * D + XPAD)              // input tile row stride
 #define NCH_I ((HO + RH - 1) / RH)
 #define NCH_J ((WO + RW - 1) / RW)
 #define NCHUNKS (BATCH * NCH_I * NCH_J)
+#define GITEMS (PC * NPAD)
+#define XITEMS (XR * XC * D)
+#define GPER ((GITEMS + NTHREADS - 1) / NTHREADS)
+#define XPER ((XITEMS + NTHREADS - 1) / NTHREADS)
 
 static_assert(PC % 2 == 0, "pixel chunk must be even");
 
@@ -69,91 +80,115 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
     const int l32 = lane & 31, h = lane >> 5;
-    const int P = gridDim.x;
     const int g = blockIdx.x;
-    const int ncb = (QTOT + CBK - 1) / CBK;
-    const int cb = blockIdx.y % ncb;
-    const int rbk = blockIdx.y / ncb;
-    const int n0 = rbk * RB, q0 = cb * CBK;
 
-    // Per lane and column tile: the LDS offset of tap q = (u, v, d) relative
-    // to the pixel's own position, or -1 past the last tap.
-    int qoff[NT];
+    // This wave's tiles: row offset into the dy tile and LDS offset of tap q
+    // relative to the pixel's own position (0 for padding columns: an
+    // in-bounds read whose result is never stored).
+    int arow[TPW], qoff[TPW], tq[TPW], tn[TPW];
+    bool tval[TPW];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int q = q0 + (wn * NT + nt) * 32 + l32;
+    for (int k = 0; k < TPW; ++k) {
+        const int lt = wave + k * NW;
+        const int t = blockIdx.y * TPB + lt;
+        tval[k] = lt < TPB && t < TILES;
+        const int rt = tval[k] ? t % NROWT : 0, ct = tval[k] ? t / NROWT : 0;
+        arow[k] = rt * 32 + l32;
+        tn[k] = rt * 32;
+        const int q = ct * 32 + l32;
+        tq[k] = q;
         if (q < QTOT) {
             const int u = q / (FW * D), rem = q % (FW * D);
-            qoff[nt] = u * XRS + rem;      // rem = v*D + d
+            qoff[k] = u * XRS + rem;      // rem = v*D + d
         } else {
-            qoff[nt] = 0;                  // any in-bounds value; never stored
+            qoff[k] = 0;
         }
     }
 
-    f32x16 acc[MT][NT];
+    f32x16 acc[TPW];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int k = 0; k < TPW; ++k)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[mt][nt][r] = 0.f;
+        for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
 
-    for (int ch = g; ch < NCHUNKS; ch += P) {
+    // Chunk staging: global -> registers (fetch) and registers -> LDS (store).
+    float greg[GPER], xreg[XPER];
+    auto fetch = [&](int ch) {
         const int b = ch / (NCH_I * NCH_J);
-        const int ci = (ch / NCH_J) % NCH_I, cj = ch % NCH_J;
-        const int i0 = ci * RH, j0 = cj * RW;
-        __syncthreads();
-        // dy chunk, [pixel][filter row in block]; zero outside.
-        for (int e = tid; e < PC * RB; e += NTHREADS) {
-            const int p = e / RB, n = e % RB;
-            const int i = i0 + p / RW, j = j0 + p % RW;
+        const int i0 = ((ch / NCH_J) % NCH_I) * RH, j0 = (ch % NCH_J) * RW;
+#pragma unroll
+        for (int r = 0; r < GPER; ++r) {
+            const int e = tid + r * NTHREADS;
             float v = 0.f;
-            if (i < HO && j < WO && n0 + n < N)
-                v = dy[(((long)b * HO + i) * WO + j) * N + n0 + n];
-            gl[p * GST + n] = v;
+            if (e < GITEMS) {
+                const int p = e / NPAD, n = e % NPAD;
+                const int i = i0 + p / RW, j = j0 + p % RW;
+                if (i < HO && j < WO && n < N) v = dy[(((long)b * HO + i) * WO + j) * N + n];
+            }
+            greg[r] = v;
         }
-        // input tile with halo, [row][col][d]; zero outside.
-        for (int e = tid; e < XR * XC * D; e += NTHREADS) {
-            const int r = e / (XC * D), rem = e % (XC * D);
-            const int ii = i0 + r, jj = j0 + rem / D;
+#pragma unroll
+        for (int r = 0; r < XPER; ++r) {
+            const int e = tid + r * NTHREADS;
             float v = 0.f;
-            if (ii < H && jj < W) v = x[(((long)b * H + ii) * W + jj) * D + rem % D];
-            xl[r * XRS + rem] = v;
+            if (e < XITEMS) {
+                const int rr = e / (XC * D), rem = e % (XC * D);
+                const int ii = i0 + rr, jj = j0 + rem / D;
+                if (ii < H && jj < W) v = x[(((long)b * H + ii) * W + jj) * D + rem % D];
+            }
+            xreg[r] = v;
         }
-        __syncthreads();
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int r = 0; r < GPER; ++r) {
+            const int e = tid + r * NTHREADS;
+            if (e < GITEMS) gl[(e / NPAD) * GST + e % NPAD] = greg[r];
+        }
+#pragma unroll
+        for (int r = 0; r < XPER; ++r) {
+            const int e = tid + r * NTHREADS;
+            if (e < XITEMS) xl[(e / (XC * D)) * XRS + e % (XC * D)] = xreg[r];
+        }
+    };
 
+    if (g < NCHUNKS) fetch(g);
+#pragma unroll 1
+    for (int ch = g; ch < NCHUNKS; ch += NP) {
+        __syncthreads();               // everyone is done with the previous chunk
+        store();
+        __syncthreads();
+#if PF
+        if (ch + NP < NCHUNKS) fetch(ch + NP);    // in flight during the compute
+#endif
         // Lane half h walks pixels [h*PC/2, (h+1)*PC/2) of the chunk.
 #pragma unroll 4
         for (int t = 0; t < PC / 2; ++t) {
             const int p = h * (PC / 2) + t;
-            const int pi = p / RW, pj = p % RW;
-            float a[MT], bb[NT];
+            const int xo = (p / RW) * XRS + (p % RW) * D;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) a[mt] = gl[p * GST + (wm * MT + mt) * 32 + l32];
-            const int xo = pi * XRS + pj * D;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) bb[nt] = xl[xo + qoff[nt]];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mt], bb[nt], acc[mt][nt], 0, 0, 0);
-        }
-    }
-
-    // Partial sums: part[g][n][q].
-    float* out = part + (long)g * N * QTOT;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int q = q0 + (wn * NT + nt) * 32 + l32;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int n = n0 + (wm * MT + mt) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (n < N && q < QTOT) out[(long)n * QTOT + q] = acc[mt][nt][r];
+            for (int k = 0; k < TPW; ++k) {
+                const float a = gl[p * GST + arow[k]];
+                const float bb = xl[xo + qoff[k]];
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
             }
         }
+#if !PF
+        if (ch + NP < NCHUNKS) fetch(ch + NP);
+#endif
+    }
+
+    // Partial sums: part[g][n][q] (zeros from workgroups without chunks).
+    float* out = part + (long)g * N * QTOT;
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+        if (!tval[k]) continue;
+        const int q = tq[k];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = tn[k] + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (n < N && q < QTOT) out[(long)n * QTOT + q] = acc[k][r];
+        }
+    }
 }
