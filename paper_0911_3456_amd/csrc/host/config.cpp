@@ -196,16 +196,21 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     const int kr = round_up(krraw, runit);
     const int rowe = (mc - 1) * s * kc + kr;
     const int rows = rowe + xpad;
-    const int wrs = kr + wpad;
-    int av;
-    if (dt == 0) av = ((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1);
-    else av = ((s * kc) % 8 == 0) ? 8 : (((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1));
+    const int wrs = (s - 1) * kc + kr + wpad;
+    int av, bv;
+    if (dt == 0) {
+        av = ((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1);
+        bv = (s == 1 || kc % 4 == 0) ? 4 : ((kc % 2 == 0) ? 2 : 1);
+    } else {
+        av = ((s * kc) % 8 == 0) ? 8 : (((s * kc) % 4 == 0) ? 4 : (((s * kc) % 2 == 0) ? 2 : 1));
+        bv = (s == 1 || kc % 8 == 0) ? 8 : ((kc % 4 == 0) ? 4 : ((kc % 2 == 0) ? 2 : 1));
+    }
     if (rows % av) { err = "igemm: xpad breaks A-read alignment"; return false; }
-    if (dt == 0 ? (wrs % 4) : (wrs % 8)) { err = "igemm: wpad breaks B-read alignment"; return false; }
+    if (wrs % bv) { err = "igemm: wpad breaks B-read alignment"; return false; }
     const int th = wm * mt * mr;
     const int tr = th + fh - 1;
     const long tile = round_up(tr * rows, 8);
-    const long wsl = (long)ustage * ncol * wrs;
+    const long wsl = (long)ustage * cb * wrs;
     const long group = (tile + 2 * wsl + 7) / 8 * 8;
     const long red = (long)(ksp - 1) * wm * wn * mt * nt * 16 * 64 * 4;
     const long lds = std::max(ksp * group * esz, red);
