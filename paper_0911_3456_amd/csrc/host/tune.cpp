@@ -81,7 +81,7 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                     for (auto& sh : shapes)
                         for (int ksp : {1, 2, 4})
                             for (int us : {1, 3})
-                                for (int pad : {0, 1}) {
+                                for (int pad : {0, 1, 2, 3}) {
                                     Config c = base;
                                     c.v["kc"] = kc;
                                     c.v["s"] = s;
@@ -92,9 +92,11 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                     if (sh[1] * sh[3] * 32 > std::max(32, ((cout * s + 31) / 32) * 32)) continue;
                                     if (sh[0] * sh[1] * sh[2] * sh[3] * ksp > 16) continue;
                                     c.v["ustage"] = us;
+                                    // LDS row padding (bank-conflict avoidance), in whole vectors
                                     const int unit = lp ? 8 : 4;
-                                    c.v["xpad"] = pad * unit;
-                                    c.v["wpad"] = pad * unit;
+                                    const int xp[] = {0, 1, 2, 3}, wp[] = {0, 1, 0, 3};
+                                    c.v["xpad"] = xp[pad] * unit;
+                                    c.v["wpad"] = wp[pad] * unit;
                                     grid.push_back(c);
                                 }
         // a coarse, deterministic subsample of the full grid (Fisher-Yates
