@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="default vs auto-tuned forward on the paper's four table shapes, then exit")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the kernels for a rocprofv3 counter pass and exit")
     ap.add_argument("--only", choices=["step", "forward", "backward_x", "backward_w"], default="step",
@@ -212,10 +214,52 @@ def batched_leg(steps: int, warmup: int):
     return out
 
 
+PAPER_SHAPES = [  # (H, W, D, N, fh, fw): the four shapes of the paper's fbconv3 table
+    (256, 256, 8, 64, 9, 9), (512, 512, 4, 32, 13, 13), (1024, 1024, 8, 16, 5, 5), (2048, 2048, 4, 4, 8, 8)]
+
+
+def paper_table(reps: int):
+    """The paper's experiment on this GPU: per table shape, the hand-written
+    default direct kernel vs the auto-tuned direct kernel ("boost"), and the
+    auto-tuned matrix-core kernel, forward GFLOP/s."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import Plan
+    dev = torch.device("cuda", 0)
+    rows = []
+    for H, W, D, N, fh, fw in PAPER_SHAPES:
+        s = wl.Shape(1, H, W, D, N, fh, fw)
+        x, w, _ = wl.draw_single(s, seed=6)
+        xt, wt = torch.from_numpy(x).to(dev), torch.from_numpy(w).to(dev)
+        row = {"input": "%dx%dx%d" % (H, W, D), "filter_bank": "%dx%dx%dx%d" % (N, fh, fw, D)}
+        pd = Plan(1, H, W, D, N, fh, fw, algo="direct", device=dev)
+        y = torch.empty(pd.y_shape, device=dev)
+        rep = pd.tune(xt, wt, y, warmup=2, reps=reps, direct_only=True)
+        row["direct_default_gflops"] = round(s.flops / rep["default_ms"] / 1e6, 1)
+        row["direct_tuned_gflops"] = round(s.flops / rep["best_ms"] / 1e6, 1)
+        row["boost"] = round(rep["default_ms"] / rep["best_ms"] - 1, 4)
+        row["direct_tuned_cfg"] = rep["best_cfg"]
+        pi = Plan(1, H, W, D, N, fh, fw, device=dev)
+        rep2 = pi.tune(xt, wt, y, warmup=2, reps=reps, max_candidates=300)
+        row["igemm_default_gflops"] = round(s.flops / rep2["default_ms"] / 1e6, 1)
+        row["igemm_tuned_gflops"] = round(s.flops / rep2["best_ms"] / 1e6, 1)
+        row["igemm_tuned_cfg"] = rep2["best_cfg"]
+        row["candidates"] = {"direct": rep["n_compiled"], "igemm": rep2["n_compiled"]}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+        pd.close()
+        pi.close()
+    return rows
+
+
 def main():
     args = parse()
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.paper_table:
+        paper_table(10)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -115,7 +115,8 @@ typedef struct fbcorr_tune_opts {
     int32_t max_candidates;
     int32_t role;      /* fbcorr_role to tune */
     uint32_t flags;    /* bit 0: also try the DIRECT algorithm for the forward role;
-                          bit 1: record the winner in the tuning database */
+                          bit 1: record the winner in the tuning database;
+                          bit 2: tune the DIRECT algorithm only (fp32 forward) */
 } fbcorr_tune_opts;
 
 typedef struct fbcorr_tune_report {

@@ -43,6 +43,6 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
                 RoleBuild& rb, std::string& err);
 
 // Tuning grids (tune.cpp).
-std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_direct);
+std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_direct, bool direct_only);
 
 }  // namespace fbc

@@ -55,7 +55,7 @@ static void add(std::vector<Config>& out, std::set<std::string>& seen, const Con
     if (seen.insert(c.str()).second) out.push_back(c);
 }
 
-std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_direct) {
+std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_direct, bool direct_only) {
     std::vector<Config> out;
     std::set<std::string> seen;
     const bool lowp = d.precision != FBCORR_FP32;
@@ -108,22 +108,25 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         }
         add(out, seen, base);
         for (auto& c : grid) add(out, seen, c);
-        if (with_direct && role == FBCORR_ROLE_FORWARD && !lowp) {
+        if (direct_only) out.clear();
+        if ((with_direct || direct_only) && role == FBCORR_ROLE_FORWARD && !lowp) {
             const Config db = default_direct(d);
             for (int th : {4, 8, 16})
                 for (int tw : {16, 32, 64})
                     for (int p : {2, 4, 8})
                         for (int q : {8, 16})
                             for (int nb : {32, 64})
-                                for (int layout : {0, 1}) {
-                                    Config c = db;
-                                    c.v["th"] = th; c.v["tw"] = tw; c.v["p"] = p; c.v["q"] = q;
-                                    c.v["nb"] = std::min(nb, ((d.N + q - 1) / q) * q);
-                                    c.v["layout"] = layout;
-                                    const int thr = th * (tw / p) * (c.v["nb"] / q);
-                                    if (thr < 64 || thr > 1024 || thr % 64) continue;
-                                    add(out, seen, c);
-                                }
+                                for (int layout : {0, 1})
+                                    for (int ds : {1, 2}) {
+                                        Config c = db;
+                                        c.v["th"] = th; c.v["tw"] = tw; c.v["p"] = p; c.v["q"] = q;
+                                        c.v["nb"] = std::min(nb, ((d.N + q - 1) / q) * q);
+                                        c.v["layout"] = layout;
+                                        c.v["ds"] = (d.D % ds == 0) ? ds : 1;
+                                        const int thr = th * (tw / p) * (c.v["nb"] / q) * c.v["ds"];
+                                        if (thr < 64 || thr > 1024 || thr % 64) continue;
+                                        add(out, seen, c);
+                                    }
         }
     } else {
         const Config base = default_config(d, role, DeviceInfo{"gfx950", 256, 160 * 1024, 1024});
@@ -246,6 +249,9 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         const int reps = (opts && opts->reps > 0) ? opts->reps : 10;
         const int maxc = (opts && opts->max_candidates > 0) ? opts->max_candidates : 1 << 30;
         const bool with_direct = opts && (opts->flags & 1u);
+        const bool direct_only = opts && (opts->flags & 4u);
+        FBC_RETURN_IF(direct_only && (role != FBCORR_ROLE_FORWARD || p->desc.precision != FBCORR_FP32),
+                      FBCORR_ERR_UNSUPPORTED, "the direct algorithm exists for the fp32 forward role only");
         fbcorr_status st;
         if ((st = check_ptr(y, "y"))) return st;
         if (role != FBCORR_ROLE_BACKWARD_X && (st = check_ptr(x, "x"))) return st;
@@ -281,7 +287,8 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         memset(&rep, 0, sizeof rep);
 
         // Default variant: the reference for the gate and the "default" time.
-        const Config dcfg = heuristic_default(d, role, p->dev);
+        Config dcfg = heuristic_default(d, role, p->dev);
+        if (direct_only) dcfg = default_direct(d);
         RoleBuild drb;
         std::string err;
         FBC_RETURN_IF(!build_role(d, role, dcfg, p->dev, drb, err), FBCORR_ERR_UNSUPPORTED, "default: " + err);
@@ -304,7 +311,7 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         snprintf(rep.default_cfg, sizeof rep.default_cfg, "%s", dcfg.str().c_str());
 
         // Candidates: resource pruning, then parallel compilation.
-        std::vector<Config> cands = tune_candidates(d, role, with_direct);
+        std::vector<Config> cands = tune_candidates(d, role, with_direct, direct_only);
         std::vector<RoleBuild> builds;
         for (auto& c : cands) {
             if ((int)builds.size() >= maxc) break;

@@ -117,9 +117,11 @@ class Plan:
                                            ctypes.c_void_p(_stream_handle(self.device))))
         return dx, dw
 
-    def tune(self, x, w, y, role="forward", warmup=2, reps=10, max_candidates=0, with_direct=False):
+    def tune(self, x, w, y, role="forward", warmup=2, reps=10, max_candidates=0, with_direct=False,
+             direct_only=False, record=False):
         ws = self.workspace(2)
-        opts = nat.TuneOpts(warmup, reps, max_candidates, nat.ROLES[role], 1 if with_direct else 0)
+        flags = (1 if with_direct else 0) | (2 if record else 0) | (4 if direct_only else 0)
+        opts = nat.TuneOpts(warmup, reps, max_candidates, nat.ROLES[role], flags)
         rep = nat.TuneReport()
         nat.check(self.lib.fbcorr_tune(self.handle, _ptr(x), _ptr(w), _ptr(y), _ptr(ws),
                                        ws.numel() if ws is not None else 0,
