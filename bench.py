@@ -17,6 +17,7 @@ Also printed in the same JSON line:
   precision     the 512x512x16 / 128x13x13x16 forward: fp32 direct,
                 fp32 matrix-core, bf16 and fp16 matrix-core times and the
                 bf16/fp16 speedups (error bounds are enforced by the tests).
+  differentiation  32 inputs 128x128x16, 64 filters 7x7x16, forward + dX + dW.
   batched       256 uneven images with their own banks in one persistent
                 launch, replayed from a HIP graph.
 """
@@ -170,6 +171,37 @@ def precision_leg(steps: int, warmup: int):
         out[k]["speedup_vs_fp32_direct"] = round(base / out[k]["ms"], 3)
     out["workload"] = "512x512x16 input, 128 filters 13x13x16 (forward only)"
     out["bf16_frac_of_peak"] = round(out["bf16_igemm"]["tflops"] / BF16_MATRIX_PEAK_TFLOPS, 4)
+    return out
+
+
+def differentiation_leg(steps: int, warmup: int):
+    """32 inputs 128x128x16, 64 filters 7x7x16: forward + dX + dW per step
+    (through the same plan calls as the autograd wrapper)."""
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import Plan
+    wk = wl.WORKLOADS["differentiation"]
+    s = wk.shape
+    x, w, rng = wl.draw_single(s, wk.seed)
+    g = wl.draw_grad(s, rng)
+    dev = torch.device("cuda", 0)
+    xt, wt, gt = (torch.from_numpy(a).to(dev) for a in (x, w, g))
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, device=dev)
+    y = torch.empty(plan.y_shape, device=dev)
+    dx, dw = torch.empty_like(xt), torch.empty_like(wt)
+
+    def step():
+        plan.forward(xt, wt, y)
+        plan.backward(xt, wt, gt, dx=dx, dw=dw)
+
+    plan.enable_timing(True)
+    sec = time_steps(step, max(5, steps // 5), warmup)
+    t = plan.read_timing()
+    out = {"workload": "32 inputs 128x128x16, 64 filters 7x7x16, forward + dX + dW",
+           "ms": round(sec * 1e3, 4), "tflops": round(3 * s.flops / sec / 1e12, 2),
+           "kernel_tflops": {r: round(s.flops / (t[r][0] / t[r][1] * 1e-3) / 1e12, 2)
+                             for r in ROLES if t[r][1]}}
+    plan.close()
     return out
 
 
@@ -353,6 +385,9 @@ def main():
     if not args.no_precision and args.only == "step":
         log("precision leg ...")
         result["precision"] = precision_leg(args.steps, args.warmup)
+    if not args.no_precision and args.only == "step":
+        log("differentiation leg ...")
+        result["differentiation"] = differentiation_leg(args.steps, args.warmup)
     if not args.no_batched and args.only == "step":
         log("batched leg ...")
         result["batched"] = batched_leg(args.steps, args.warmup)
