@@ -72,6 +72,7 @@ static Config batched_variant_config(int D, int N) {
     c.v["mr"] = 2;
     c.v["ustage"] = 1;
     c.v["kc"] = D <= 16 ? D : 16;
+    c.v["mf"] = 32;
     return c;
 }
 
@@ -103,9 +104,9 @@ static bool generate(BatchedState& st, const DeviceInfo& di, KernelSource& ks, s
     src << "// Generated persistent batched filter-bank correlation: " << st.vars.size() << " variant(s).\n";
     src << "#define FB_BATCHED 1\n" << header;
     int maxlds = 16;
-    const char* keys[] = {"kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage"};
-    const char* defs[] = {"FB_KC", "FB_S", "FB_MR", "FB_MT", "FB_NT", "FB_WM", "FB_WN", "FB_KS", "FB_XPAD",
-                          "FB_WPAD", "FB_USTAGE"};
+    const char* keys[] = {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage"};
+    const char* defs[] = {"FB_MF", "FB_KC", "FB_S", "FB_MR", "FB_MT", "FB_NT", "FB_WM", "FB_WN", "FB_KS",
+                          "FB_XPAD", "FB_WPAD", "FB_USTAGE"};
     for (size_t v = 0; v < st.vars.size(); ++v) {
         const BVariant& bv = st.vars[v];
         src << "\n// ---- variant " << v << ": fh=" << bv.fh << " fw=" << bv.fw << " D=" << bv.D << " N=" << bv.N
@@ -227,8 +228,9 @@ static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const
             FBC_RETURN_IF(!ok, FBCORR_ERR_UNSUPPORTED, "no batched variant fits for key: " + err);
             const int s = bv.cfg.get("s");
             bv.th = bv.cfg.get("wm") * bv.cfg.get("mt") * bv.cfg.get("mr");
-            bv.two = s * (32 / bv.cfg.get("mr"));
-            bv.cb = bv.cfg.get("wn") * bv.cfg.get("nt") * 32 / s;
+            const int mf = bv.cfg.get("mf");
+            bv.two = s * (mf / bv.cfg.get("mr"));
+            bv.cb = bv.cfg.get("wn") * bv.cfg.get("nt") * mf / s;
             bv.lds = rb.main_geom.lds;
             it = keyidx.emplace(key, (int)st->vars.size()).first;
             st->vars.push_back(bv);

@@ -83,7 +83,7 @@ Config default_igemm(int cin, int cout, bool lowp) {
     const int nt = cols >= 64 ? 2 : 1;
     const int kc = pick_kc(cin, lowp);
     const int nchunk = (cin + kc - 1) / kc;
-    c.v = {{"kc", kc}, {"s", s}, {"mr", s >= 2 ? 4 : 1}, {"mt", 1}, {"nt", nt}, {"wm", s >= 2 ? 1 : 4},
+    c.v = {{"mf", 32}, {"kc", kc}, {"s", s}, {"mr", s >= 2 ? 4 : 1}, {"mt", 1}, {"nt", nt}, {"wm", s >= 2 ? 1 : 4},
            {"wn", 1}, {"ks", s >= 2 ? std::min(4, nchunk) : 1}, {"xpad", lowp ? 8 : 4},
            {"wpad", lowp ? 8 : 4}, {"ustage", 1}, {"xcd", 1}};
     return c;
@@ -176,22 +176,25 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     const int wm = c.get("wm"), wn = c.get("wn"), xpad = c.get("xpad"), wpad = c.get("wpad");
     const int ustage = std::min(c.get("ustage"), fh), xcd = c.get("xcd");
     const int mr = c.get("mr"), ksp = c.get("ks");
+    const int mf = c.v.count("mf") ? c.get("mf") : 32;
     if (kc < 1 || s < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || xpad < 0 || wpad < 0 || ustage < 1 ||
         mr < 1 || ksp < 1) {
         err = "igemm: every knob must be positive"; return false;
     }
+    if (mf != 32 && mf != 16) { err = "igemm: mf must be 32 or 16"; return false; }
     if (s != 1 && s != 2 && s != 4 && s != 8) { err = "igemm: s must be 1, 2, 4 or 8"; return false; }
-    if (32 % mr) { err = "igemm: mr must divide 32"; return false; }
+    if (mf % mr) { err = "igemm: mr must divide mf"; return false; }
     const int threads = wm * wn * ksp * 64;
     if (threads > std::min(1024, di.max_threads)) { err = "igemm: too many threads"; return false; }
-    if (mt * nt > 8) { err = "igemm: more than 8 accumulator tiles per wave"; return false; }
-    const int ncol = wn * nt * 32;
+    const int nreg = mf * mf / 64;
+    if (mt * nt * nreg > 128) { err = "igemm: more than 128 accumulator registers per lane"; return false; }
+    const int ncol = wn * nt * mf;
     if (ncol % s) { err = "igemm: columns must split evenly into shifts"; return false; }
     const int cb = ncol / s;
-    const int mc = 32 / mr;
+    const int mc = mf / mr;
     const int ho = hi + 2 * padh - fh + 1, wo = wi + 2 * padw - fw + 1;
     const int esz = dt == 0 ? 4 : 2;
-    const int runit = dt == 0 ? 8 : 16;
+    const int runit = (64 / mf) * (dt == 0 ? 4 : 8);
     const int krraw = (fw + s - 1) * kc;
     const int kr = round_up(krraw, runit);
     const int rowe = (mc - 1) * s * kc + kr;
@@ -212,7 +215,7 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     const long tile = round_up(tr * rows, 8);
     const long wsl = (long)ustage * cb * wrs;
     const long group = (tile + 2 * wsl + 7) / 8 * 8;
-    const long red = (long)(ksp - 1) * wm * wn * mt * nt * 16 * 64 * 4;
+    const long red = (long)(ksp - 1) * wm * wn * mt * nt * nreg * 64 * 4;
     const long lds = std::max(ksp * group * esz, red);
     if (lds > di.lds_per_block) { err = "igemm: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
     const long grid = (long)cdiv(wo, s * mc) * cdiv(ho, th) * cdiv(cout, cb) * batch;
@@ -230,7 +233,7 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "CIN", cin); opt(ks.options, "COUT", cout);
     opt(ks.options, "HI", hi); opt(ks.options, "WI", wi); opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
     opt(ks.options, "PADH", padh); opt(ks.options, "PADW", padw);
-    opt(ks.options, "KC", kc); opt(ks.options, "S", s); opt(ks.options, "MR", mr);
+    opt(ks.options, "MF", mf); opt(ks.options, "KC", kc); opt(ks.options, "S", s); opt(ks.options, "MR", mr);
     opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
     opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "KS", ksp); opt(ks.options, "DT", dt);
     opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad);
@@ -347,7 +350,7 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
 
 static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
-        {"igemm", {"kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd"}},
+        {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf"}},
     };

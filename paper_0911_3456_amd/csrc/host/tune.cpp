@@ -77,19 +77,22 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         std::vector<Config> grid;
         for (int kc : kcs)
             for (int s : ss)
+              for (int mf : {32, 16})
                 for (int mr : {1, 2, 4, 8})
                     for (auto& sh : shapes)
                         for (int ksp : {1, 2, 4})
                             for (int us : {1, 3})
                                 for (int pad : {0, 1, 2, 3}) {
                                     Config c = base;
+                                    c.v["mf"] = mf;
                                     c.v["kc"] = kc;
-                                    c.v["s"] = s;
+                                    c.v["s"] = mf == 16 ? std::max(1, s / 2) : s;
                                     c.v["mr"] = mr;
                                     c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
                                     c.v["ks"] = ksp;
                                     // skip tiles whose columns exceed what the channels can fill
-                                    if (sh[1] * sh[3] * 32 > std::max(32, ((cout * s + 31) / 32) * 32)) continue;
+                                    const int cs = c.v["s"];
+                                    if (sh[1] * sh[3] * mf > std::max(mf, ((cout * cs + mf - 1) / mf) * mf)) continue;
                                     if (sh[0] * sh[1] * sh[2] * sh[3] * ksp > 16) continue;
                                     c.v["ustage"] = us;
                                     // LDS row padding (bank-conflict avoidance), in whole vectors

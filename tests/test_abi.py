@@ -163,6 +163,11 @@ def test_gpu_test_configurations_are_valid():
         fb.codegen(d, "backward_x", "algo=igemm " + c)
     for c in tb.BW_CFGS:
         fb.codegen(d, "backward_w", "algo=dw " + c)
+    import test_gpu_precision as tp
+    d = fb.make_desc(2, 45, 60, 16, 64, 7, 7, precision="bf16")
+    for c in tp.LOWP_CFGS:
+        if c:
+            fb.codegen(d, "forward", c)
 
 
 def test_disk_cache_reuse_and_corruption(tmp_path, monkeypatch):

@@ -81,7 +81,8 @@ def test_one_gradient_at_a_time():
     np.testing.assert_array_equal(dw, rw.astype(np.float32))
 
 
-BX_CFGS = ["kc=4 s=4 mr=4 mt=1 nt=1 wm=1 wn=1 ks=4", "kc=4 s=4 mr=2 mt=2 nt=1 wm=1 wn=1 ks=2 ustage=3",
+BX_CFGS = ["mf=16 kc=4 s=2 mr=4 mt=2 nt=1 wm=2 wn=1 ks=4", "mf=16 kc=8 s=1 mr=2 mt=1 nt=1 wm=2 wn=1 ks=2",
+           "kc=4 s=4 mr=4 mt=1 nt=1 wm=1 wn=1 ks=4", "kc=4 s=4 mr=2 mt=2 nt=1 wm=1 wn=1 ks=2 ustage=3",
            "kc=8 s=2 mr=4 mt=1 nt=1 wm=2 wn=1 ks=3", "kc=8 s=4 mt=1 nt=1 wm=4 wn=1", "kc=8 s=2 mr=1 ks=1 mt=2 nt=1 wm=2 wn=1 ustage=3",
            "kc=4 s=8 mt=1 nt=1 wm=2 wn=1 xcd=0", "kc=8 s=1 mt=1 nt=1 wm=4 wn=1"]
 BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=0",

@@ -84,6 +84,9 @@ def test_random_fp32(shape):
 
 
 IGEMM_CFGS = [
+    "mf=16 kc=8 s=1 mr=4 mt=2 nt=2 wm=2 wn=1 ks=1",
+    "mf=16 kc=4 s=2 mr=2 mt=1 nt=1 wm=2 wn=2 ks=2 ustage=3",
+    "mf=16 kc=8 s=1 mr=16 mt=1 nt=4 wm=1 wn=1 ks=3",
     "kc=8 s=1 mr=4 mt=1 nt=2 wm=2 wn=1 ks=2",
     "kc=4 s=2 mr=2 mt=2 nt=1 wm=1 wn=2 ks=2 ustage=1",
     "kc=8 s=1 mr=8 mt=1 nt=1 wm=1 wn=2 ks=3 ustage=1 xpad=0",

@@ -56,14 +56,22 @@ def test_lowp_error_bounds(shape, prec):
     assert e2 <= 1e-5
 
 
+LOWP_CFGS = [None, "algo=igemm mf=16 kc=16 s=1 mr=4 mt=2 nt=2 wm=2 wn=1 ks=1",
+             "algo=igemm mf=32 kc=8 s=1 mr=2 mt=2 nt=2 wm=2 wn=1 ks=2"]
+
+
+@pytest.mark.parametrize("cfg", LOWP_CFGS)
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-def test_lowp_integer_exact(prec):
+def test_lowp_integer_exact(prec, cfg):
     need_gpu()
     s = wl.Shape(2, 45, 60, 16, 64, 7, 7)
     x, w, _ = wl.draw_integer(s, seed=77)
     w[3] = 0.0        # an all-zero filter (scale 1)
     w[5] *= 0.125     # power-of-two scaled filter
-    y = host(_plan(s, precision=prec).forward(*to_dev(x, w)))
+    plan = _plan(s, precision=prec)
+    if cfg:
+        plan.set_config("forward", cfg)
+    y = host(plan.forward(*to_dev(x, w)))
     np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
 
 
