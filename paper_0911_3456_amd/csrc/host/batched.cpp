@@ -199,9 +199,25 @@ std::string batched_describe(const Plan* p) {
 
 // Plan-time work shared by the device and the offline paths: variants, the
 // work table, the workspace layout and the generated source.
+using KeyT = std::tuple<int, int, int, int>;
+
+// The tuning-database key of a batched variant: role "batched", extents 0.
+static fbcorr_desc variant_key_desc(int fh, int fw, int D, int N) {
+    fbcorr_desc k{};
+    k.batch = 1; k.H = 0; k.W = 0; k.D = D; k.N = N; k.fh = fh; k.fw = fw;
+    k.precision = FBCORR_FP32; k.algo = FBCORR_ALGO_AUTO; k.flags = 0;
+    return k;
+}
+static const int kRoleBatched = 3;
+
+static bool four_waves(const Config& c) {
+    return c.algo == "igemm" && c.get("wm") * c.get("wn") * c.get("ks") == 4;
+}
+
 static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const fbcorr_desc* descs,
-                                     BatchedState* st, KernelSource& ks) {
-    std::map<std::tuple<int, int, int, int>, int> keyidx;
+                                     BatchedState* st, KernelSource& ks,
+                                     const std::map<KeyT, Config>* overrides = nullptr) {
+    std::map<KeyT, int> keyidx;
     for (int32_t i = 0; i < count; ++i) {
         fbcorr_desc d = descs[i];
         fbcorr_status s0 = validate_desc(&d);
@@ -213,10 +229,26 @@ static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const
         auto it = keyidx.find(key);
         if (it == keyidx.end()) {
             BVariant bv{d.fh, d.fw, d.D, d.N, batched_variant_config(d.D, d.N), 0, 0, 0, 0};
-            // shrink until the variant fits the device
             RoleBuild rb;
             std::string err;
             bool ok = false;
+            // a tuned configuration for this key: from the caller, else the database
+            Config tuned;
+            bool have = false;
+            if (overrides) {
+                auto o = overrides->find(key);
+                if (o != overrides->end()) { tuned = o->second; have = true; }
+            }
+            std::string text;
+            if (!have && tuning_db_lookup(dev.arch, kRoleBatched, variant_key_desc(d.fh, d.fw, d.D, d.N), text)) {
+                tuned = bv.cfg;
+                have = parse_config(text, tuned, err);
+            }
+            if (have && four_waves(tuned) && build_role(d, FBCORR_ROLE_FORWARD, tuned, dev, rb, err)) {
+                bv.cfg = tuned;
+                ok = true;
+            }
+            // otherwise the heuristic, shrunk until it fits the device
             for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
                 ok = build_role(d, FBCORR_ROLE_FORWARD, bv.cfg, dev, rb, err);
                 if (!ok) {
@@ -302,6 +334,102 @@ static fbcorr_status launch_batched(Plan* p, const float* const* xs, const float
     r = launch(st->kernel, LaunchGeom{st->grid, 1, 256, 0}, s, a1);
     timing_end(p, FBCORR_ROLE_FORWARD, s, ev);
     return r;
+}
+
+// Representative problem of a variant: its largest image.
+static fbcorr_desc variant_rep(const BatchedState* st, size_t v) {
+    const BVariant& bv = st->vars[v];
+    fbcorr_desc best{};
+    double bf = -1;
+    for (size_t i = 0; i < st->descs.size(); ++i) {
+        if (st->img_var[i] != (int)v) continue;
+        const fbcorr_desc& d = st->descs[i];
+        const double f = (double)(d.H - d.fh + 1) * (d.W - d.fw + 1);
+        if (f > bf) { bf = f; best = d; }
+    }
+    (void)bv;
+    return best;
+}
+
+size_t batched_tune_workspace(const Plan* p) {
+    size_t need = 0;
+    if (!p->bstate) return 0;
+    for (size_t v = 0; v < p->bstate->vars.size(); ++v) {
+        Plan tmp;
+        tmp.desc = variant_rep(p->bstate, v);
+        tmp.device = p->device;
+        tmp.dev = p->dev;
+        need = std::max(need, tune_workspace(&tmp));
+    }
+    return need;
+}
+
+// Per-key tuning of a batched plan (Sec. 6.2: the best variant differs per
+// input): each variant is tuned on its largest image among four-wave
+// implicit-GEMM candidates, then the persistent kernel is regenerated.
+fbcorr_status tune_batched(Plan* p, void* workspace, size_t workspace_bytes, hipStream_t s,
+                           const fbcorr_tune_opts* opts, fbcorr_tune_report* report) {
+    BatchedState* st = p->bstate;
+    FBC_RETURN_IF(!st, FBCORR_ERR_INVALID_ARGUMENT, "not a batched plan");
+    fbcorr_tune_opts o{};
+    if (opts) o = *opts;
+    o.role = FBCORR_ROLE_FORWARD;
+    o.flags &= ~(1u | 4u);      // no direct variants in the persistent kernel
+    const bool record = opts && (opts->flags & 2u);
+    fbcorr_tune_report total;
+    memset(&total, 0, sizeof total);
+    std::map<KeyT, Config> chosen;
+    for (size_t v = 0; v < st->vars.size(); ++v) {
+        const BVariant& bv = st->vars[v];
+        Plan tmp;
+        tmp.desc = variant_rep(st, v);
+        tmp.device = p->device;
+        tmp.dev = p->dev;
+        fbcorr_tune_report r;
+        Config best;
+        fbcorr_status e = tune_plan(&tmp, nullptr, nullptr, nullptr, workspace, workspace_bytes, s, &o, true, false,
+                                    &r, &best);
+        if (e != FBCORR_OK) return e;
+        total.n_tried += r.n_tried;
+        total.n_compiled += r.n_compiled;
+        total.n_rejected_resources += r.n_rejected_resources;
+        total.n_rejected_parity += r.n_rejected_parity;
+        total.n_failed += r.n_failed;
+        total.best_ms += r.best_ms;
+        total.default_ms += r.default_ms;
+        const KeyT key = std::make_tuple(bv.fh, bv.fw, bv.D, bv.N);
+        if (four_waves(best)) {
+            chosen[key] = best;
+            if (record) {
+                std::string err;
+                FBC_RETURN_IF(!tuning_db_record(p->dev.arch, kRoleBatched, variant_key_desc(bv.fh, bv.fw, bv.D, bv.N),
+                                                best.str(), err),
+                              FBCORR_ERR_INTERNAL, err);
+            }
+        }
+    }
+    // regenerate the persistent kernel with the chosen variants
+    std::unique_ptr<BatchedState> ns(new BatchedState());
+    KernelSource ks;
+    fbcorr_status e = prepare_batched(p->dev, (int32_t)st->descs.size(), st->descs.data(), ns.get(), ks, &chosen);
+    if (e != FBCORR_OK) return e;
+    e = load_kernel(ks, p->device, ns->kernel);
+    if (e != FBCORR_OK) return e;
+    KernelSource rs = ks;
+    rs.name = "fbcorr_batched_reset";
+    e = load_kernel(rs, p->device, ns->reset);
+    if (e != FBCORR_OK) return e;
+    int per_cu = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns->kernel.fn, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    ns->grid = (int)std::max<int64_t>(1, std::min<int64_t>(ns->nitems, (int64_t)p->dev.cus * per_cu));
+    destroy_batched(p);
+    p->batch_ws = ns->ws_bytes;
+    p->bstate = ns.release();
+    snprintf(total.best_cfg, sizeof total.best_cfg, "%zu variants tuned", chosen.size());
+    snprintf(total.default_cfg, sizeof total.default_cfg, "per-key heuristics");
+    if (report) *report = total;
+    return FBCORR_OK;
 }
 
 }  // namespace fbc

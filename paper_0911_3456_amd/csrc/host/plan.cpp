@@ -244,7 +244,7 @@ fbcorr_status fbcorr_workspace_size(fbcorr_plan_t plan, int pass, size_t* bytes)
     Plan* p = reinterpret_cast<Plan*>(plan);
     FBC_RETURN_IF(!p || !bytes, FBCORR_ERR_INVALID_ARGUMENT, "NULL argument");
     if (p->batched) {
-        *bytes = p->batch_ws;
+        *bytes = pass == 2 ? batched_tune_workspace(p) : p->batch_ws;
         return FBCORR_OK;
     }
     DeviceGuard g(p->device);

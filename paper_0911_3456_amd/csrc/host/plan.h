@@ -58,6 +58,13 @@ void timing_end(Plan* p, int role, hipStream_t s, hipEvent_t a);
 
 // tune.cpp
 size_t tune_workspace(Plan* p);
+fbcorr_status tune_plan(Plan* p, const float* x, const float* w, float* y, void* workspace, size_t workspace_bytes,
+                        hipStream_t s, const fbcorr_tune_opts* opts, bool four_waves, bool install,
+                        fbcorr_tune_report* report, Config* chosen_out);
+// batched.cpp
+fbcorr_status tune_batched(Plan* p, void* workspace, size_t workspace_bytes, hipStream_t s,
+                           const fbcorr_tune_opts* opts, fbcorr_tune_report* report);
+size_t batched_tune_workspace(const Plan* p);
 // batched.cpp
 void destroy_batched(Plan* p);
 std::string batched_describe(const Plan* p);

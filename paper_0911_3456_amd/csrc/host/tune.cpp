@@ -238,14 +238,16 @@ static fbcorr_status make_exec(Plan* p, int role, const RoleBuild& rb, RoleExec&
 
 using namespace fbc;
 
-extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const float* w, float* y, void* workspace,
-                                     size_t workspace_bytes, void* stream, const fbcorr_tune_opts* opts,
-                                     fbcorr_tune_report* report) {
-    try {
-        clear_error();
-        Plan* p = reinterpret_cast<Plan*>(plan);
-        FBC_RETURN_IF(!p, FBCORR_ERR_INVALID_ARGUMENT, "plan is NULL");
-        FBC_RETURN_IF(p->batched, FBCORR_ERR_UNSUPPORTED, "batched plans are tuned per key at plan time");
+namespace fbc {
+
+// The tuning loop for one plan and role.  x, w, y may be NULL: then the
+// timing runs on the integer gate data as well.  With four_waves only
+// implicit-GEMM variants of exactly four waves are tried (the block size of
+// the persistent batched kernel).  install: put the winner into the plan.
+fbcorr_status tune_plan(Plan* p, const float* x, const float* w, float* y, void* workspace,
+                        size_t workspace_bytes, hipStream_t s, const fbcorr_tune_opts* opts, bool four_waves,
+                        bool install, fbcorr_tune_report* report, Config* chosen_out) {
+    {
         const int role = opts ? opts->role : FBCORR_ROLE_FORWARD;
         FBC_RETURN_IF(role < 0 || role >= FBCORR_ROLE_COUNT, FBCORR_ERR_INVALID_ARGUMENT, "unknown role");
         const int warmup = (opts && opts->warmup > 0) ? opts->warmup : 2;
@@ -256,13 +258,14 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         FBC_RETURN_IF(direct_only && (role != FBCORR_ROLE_FORWARD || p->desc.precision != FBCORR_FP32),
                       FBCORR_ERR_UNSUPPORTED, "the direct algorithm exists for the fp32 forward role only");
         fbcorr_status st;
-        if ((st = check_ptr(y, "y"))) return st;
-        if (role != FBCORR_ROLE_BACKWARD_X && (st = check_ptr(x, "x"))) return st;
-        if (role != FBCORR_ROLE_BACKWARD_W && (st = check_ptr(w, "w"))) return st;
-        DeviceGuard guard(p->device);
+        const bool own_data = !x && !w && !y;
+        if (!own_data) {
+            if ((st = check_ptr(y, "y"))) return st;
+            if (role != FBCORR_ROLE_BACKWARD_X && (st = check_ptr(x, "x"))) return st;
+            if (role != FBCORR_ROLE_BACKWARD_W && (st = check_ptr(w, "w"))) return st;
+        }
         const TuneLayout t = tune_layout(p);
         if ((st = check_ws(workspace, workspace_bytes, t.total))) return st;
-        hipStream_t s = (hipStream_t)stream;
         char* base = (char*)workspace;
         const fbcorr_desc& d = p->desc;
 
@@ -283,7 +286,7 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
             (st = fill_int(p, gi, t.ny, 37u, R, s)))
             return st;
         const TuneBuffers gate{xi, wi, gi, nullptr, rws};
-        const TuneBuffers timed{x, w, y, nullptr, rws};
+        const TuneBuffers timed = own_data ? TuneBuffers{xi, wi, gi, nullptr, rws} : TuneBuffers{x, w, y, nullptr, rws};
         const size_t nout = out_elems(t, role);
 
         fbcorr_tune_report rep;
@@ -307,7 +310,7 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         float refmax = 0.f;
         for (float v : href) refmax = std::max(refmax, std::fabs(v));
         TuneBuffers t1 = timed;
-        t1.out = role == FBCORR_ROLE_FORWARD ? y : cand;
+        t1.out = (role == FBCORR_ROLE_FORWARD && !own_data) ? y : cand;
         double dms = 0;
         if ((st = time_role(p, role, dex, t1, s, warmup, reps, dms))) return st;
         rep.default_ms = dms;
@@ -318,6 +321,7 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         std::vector<RoleBuild> builds;
         for (auto& c : cands) {
             if ((int)builds.size() >= maxc) break;
+            if (four_waves && (c.algo != "igemm" || c.get("wm") * c.get("wn") * c.get("ks") != 4)) continue;
             RoleBuild rb;
             rep.n_tried++;
             if (!build_role(d, role, c, p->dev, rb, err)) { rep.n_rejected_resources++; continue; }
@@ -364,7 +368,7 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
             }
             if (!same) { rep.n_rejected_parity++; continue; }
             TuneBuffers t2 = timed;
-            t2.out = role == FBCORR_ROLE_FORWARD ? y : cand;
+            t2.out = (role == FBCORR_ROLE_FORWARD && !own_data) ? y : cand;
             double ms = 0;
             if (time_role(p, role, ex, t2, s, warmup, reps, ms) != FBCORR_OK) { rep.n_failed++; continue; }
             if (ms < best) { best = ms; best_i = (int)j; }
@@ -372,14 +376,34 @@ extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const f
         const Config& chosen = best_i >= 0 ? builds[best_i].cfg : dcfg;
         rep.best_ms = best;
         snprintf(rep.best_cfg, sizeof rep.best_cfg, "%s", chosen.str().c_str());
-        st = compile_role(p, role, chosen);
-        if (st != FBCORR_OK) return st;
-        if (opts && (opts->flags & 2u)) {
-            std::string e2;
-            FBC_RETURN_IF(!tuning_db_record(p->dev.arch, role, d, chosen.str(), e2), FBCORR_ERR_INTERNAL, e2);
+        if (chosen_out) *chosen_out = chosen;
+        if (install) {
+            st = compile_role(p, role, chosen);
+            if (st != FBCORR_OK) return st;
+            if (opts && (opts->flags & 2u)) {
+                std::string e2;
+                FBC_RETURN_IF(!tuning_db_record(p->dev.arch, role, d, chosen.str(), e2), FBCORR_ERR_INTERNAL, e2);
+            }
         }
         if (report) *report = rep;
         return FBCORR_OK;
+    }
+}
+
+}  // namespace fbc
+
+extern "C" fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const float* w, float* y, void* workspace,
+                                     size_t workspace_bytes, void* stream, const fbcorr_tune_opts* opts,
+                                     fbcorr_tune_report* report) {
+    try {
+        clear_error();
+        Plan* p = reinterpret_cast<Plan*>(plan);
+        FBC_RETURN_IF(!p, FBCORR_ERR_INVALID_ARGUMENT, "plan is NULL");
+        DeviceGuard guard(p->device);
+        if (p->batched) return tune_batched(p, workspace, workspace_bytes, (hipStream_t)stream, opts, report);
+        FBC_RETURN_IF(!x && !w && !y, FBCORR_ERR_INVALID_ARGUMENT, "x, w and y are NULL");
+        return tune_plan(p, x, w, y, workspace, workspace_bytes, (hipStream_t)stream, opts, false, true, report,
+                         nullptr);
     } catch (const std::exception& e) {
         set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what());
         return FBCORR_ERR_INTERNAL;

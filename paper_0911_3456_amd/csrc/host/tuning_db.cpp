@@ -27,7 +27,7 @@ bool g_db_loaded = false;
 std::map<std::string, std::string> g_db;
 }  // namespace
 
-static const char* kRoleNames[] = {"forward", "backward_x", "backward_w"};
+static const char* kRoleNames[] = {"forward", "backward_x", "backward_w", "batched"};
 static const char* kPrecNames[] = {"fp32", "bf16", "fp16"};
 
 std::string tuning_db_path() {

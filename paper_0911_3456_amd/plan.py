@@ -220,16 +220,32 @@ class BatchedPlan:
         h = ctypes.c_void_p()
         nat.check(self.lib.fbcorr_plan_batched(len(descs), arr, self.device.index, ctypes.byref(h)))
         self.handle = h
-        n = ctypes.c_size_t()
-        nat.check(self.lib.fbcorr_workspace_size(h, 0, ctypes.byref(n)))
-        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
-        off = (-ws.data_ptr()) % 256
-        self.ws = ws[off:off + n.value]
+        self.ws = self._workspace(0)
         # device arrays of pointers; their addresses stay fixed for graph replay
         k = len(self.shapes)
         self.px = torch.zeros(k, dtype=torch.int64, device=self.device)
         self.pw = torch.zeros(k, dtype=torch.int64, device=self.device)
         self.py = torch.zeros(k, dtype=torch.int64, device=self.device)
+
+    def _workspace(self, pass_: int):
+        n = ctypes.c_size_t()
+        nat.check(self.lib.fbcorr_workspace_size(self.handle, pass_, ctypes.byref(n)))
+        ws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        return ws[off:off + n.value]
+
+    def tune(self, max_candidates=40, warmup=1, reps=5, record=False):
+        """Tune every (fh, fw, D, N) variant on its largest image (four-wave
+        candidates) and regenerate the persistent kernel."""
+        ws = self._workspace(2)
+        opts = nat.TuneOpts(warmup, reps, max_candidates, 0, 2 if record else 0)
+        rep = nat.TuneReport()
+        nat.check(self.lib.fbcorr_tune(self.handle, None, None, None, _ptr(ws), ws.numel(),
+                                       ctypes.c_void_p(_stream_handle(self.device)),
+                                       ctypes.byref(opts), ctypes.byref(rep)))
+        del ws
+        self.ws = self._workspace(0)     # the work table may have changed size
+        return rep.as_dict()
 
     @property
     def flops(self) -> int:

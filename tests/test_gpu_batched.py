@@ -128,3 +128,22 @@ def test_batching_workload_sampled():
         worst = max(worst, e)
     print("batching workload: worst sampled normalised error %.3e" % worst)
     assert worst <= 1e-5
+
+
+def test_batched_per_key_tuning_keeps_parity():
+    """Tuning picks a four-wave variant per key; results stay exact."""
+    need_gpu()
+    from paper_0911_3456_amd import BatchedPlan
+    shapes = SMALL[:4]
+    rng = np.random.default_rng(8)
+    xs = [rng.integers(-4, 5, size=(s.H, s.W, s.D)).astype(np.float32) for s in shapes]
+    fs = [rng.integers(-4, 5, size=(s.N, s.fh, s.fw, s.D)).astype(np.float32) for s in shapes]
+    plan = BatchedPlan([(s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes])
+    before = plan.describe()
+    rep = plan.tune(max_candidates=6, warmup=1, reps=2)
+    print(rep, plan.describe())
+    assert rep["n_compiled"] >= 1 and rep["n_rejected_parity"] == 0
+    ys = plan.forward(_dev(xs), _dev(fs))
+    for i in range(len(shapes)):
+        np.testing.assert_array_equal(host(ys[i]), oracle.forward(xs[i], fs[i]).astype(np.float32))
+    assert "variants=3" in before
