@@ -34,7 +34,7 @@ struct BatchedState {
     std::vector<int32_t> items;     // 4 ints per item: variant, image, tile, 0
     std::vector<int32_t> imgs;      // 4 ints per image: H, W, Ho, Wo
     Kernel kernel, reset;
-    int grid = 0, threads = 256;
+    int grid = 0, threads = 256, per_cu = 1;
     size_t off_counter = 0, off_items = 0, off_imgs = 0, ws_bytes = 0;
     int64_t nitems = 0;
     double flops = 0;
@@ -189,7 +189,7 @@ std::string batched_describe(const Plan* p) {
     if (!p->bstate) return "batched";
     std::ostringstream os;
     os << "batched images=" << p->bstate->descs.size() << " variants=" << p->bstate->vars.size()
-       << " items=" << p->bstate->nitems << " grid=" << p->bstate->grid;
+       << " items=" << p->bstate->nitems << " grid=" << p->bstate->grid << " per_cu=" << p->bstate->per_cu;
     for (size_t v = 0; v < p->bstate->vars.size(); ++v) {
         const BVariant& b = p->bstate->vars[v];
         os << " | v" << v << " fh=" << b.fh << " fw=" << b.fw << " D=" << b.D << " N=" << b.N << " " << b.cfg.str();
@@ -244,7 +244,8 @@ static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const
                 tuned = bv.cfg;
                 have = parse_config(text, tuned, err);
             }
-            if (have && four_waves(tuned) && build_role(d, FBCORR_ROLE_FORWARD, tuned, dev, rb, err)) {
+            if (have && four_waves(tuned) && build_role(d, FBCORR_ROLE_FORWARD, tuned, dev, rb, err) &&
+                rb.main_geom.lds <= dev.lds_per_block / 2) {
                 bv.cfg = tuned;
                 ok = true;
             }
@@ -310,6 +311,7 @@ static fbcorr_status build_batched(Plan* p, int32_t count, const fbcorr_desc* de
     int per_cu = 0;
     hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, st->kernel.fn, 256, 0);
     if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    st->per_cu = per_cu;
     st->grid = (int)std::min<int64_t>(st->nitems, (int64_t)p->dev.cus * per_cu);
     st->grid = std::max(st->grid, 1);
     p->batch_ws = st->ws_bytes;
@@ -422,6 +424,7 @@ fbcorr_status tune_batched(Plan* p, void* workspace, size_t workspace_bytes, hip
     int per_cu = 0;
     if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ns->kernel.fn, 256, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    ns->per_cu = per_cu;
     ns->grid = (int)std::max<int64_t>(1, std::min<int64_t>(ns->nitems, (int64_t)p->dev.cus * per_cu));
     destroy_batched(p);
     p->batch_ws = ns->ws_bytes;

@@ -325,6 +325,8 @@ fbcorr_status tune_plan(Plan* p, const float* x, const float* w, float* y, void*
             RoleBuild rb;
             rep.n_tried++;
             if (!build_role(d, role, c, p->dev, rb, err)) { rep.n_rejected_resources++; continue; }
+            // batched variants share one kernel: keep two workgroups per CU
+            if (four_waves && rb.main_geom.lds > p->dev.lds_per_block / 2) { rep.n_rejected_resources++; continue; }
             if (rb.ws_bytes > workspace_bytes - t.role_ws) { rep.n_rejected_resources++; continue; }
             builds.push_back(rb);
         }
