@@ -232,6 +232,13 @@ fbcorr_status fbcorr_plan_destroy(fbcorr_plan_t plan) {
     if (!p) return FBCORR_OK;
     for (auto& v : p->pending)
         for (auto& e : v) { hipEventDestroy(e.first); hipEventDestroy(e.second); }
+    if (p->side) {
+        DeviceGuard g(p->device);
+        hipStreamSynchronize(p->side);
+        hipEventDestroy(p->fork);
+        hipEventDestroy(p->join);
+        hipStreamDestroy(p->side);
+    }
     destroy_batched(p);
     delete p;
     return FBCORR_OK;
@@ -302,6 +309,29 @@ fbcorr_status fbcorr_backward(fbcorr_plan_t plan, const float* x, const float* w
     const size_t need = backward_ws(p, &off_w);
     if ((st = check_ws(workspace, workspace_bytes, need))) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (dx && dw) {
+        // The two gradients are independent: dW goes to a side stream forked
+        // from the caller's stream and joined back, so the tail of one
+        // kernel overlaps the other.  (Default-priority stream; the event
+        // pair also works under graph capture.)
+        if (!p->side) {
+            hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+            FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("side stream: ") + hipGetErrorString(e));
+        }
+        hipError_t e = hipEventRecord(p->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork, 0);
+        FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("fork: ") + hipGetErrorString(e));
+        st = run_backward_w(p, p->role[FBCORR_ROLE_BACKWARD_W], x, dy, dw, (char*)workspace + off_w, p->side);
+        fbcorr_status st2 = run_backward_x(p, p->role[FBCORR_ROLE_BACKWARD_X], w, dy, dx, workspace, s);
+        e = hipEventRecord(p->join, p->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+        if (st != FBCORR_OK) return st;
+        if (st2 != FBCORR_OK) return st2;
+        FBC_RETURN_IF(e != hipSuccess, FBCORR_ERR_LAUNCH, std::string("join: ") + hipGetErrorString(e));
+        return FBCORR_OK;
+    }
     if (dx) {
         st = run_backward_x(p, p->role[FBCORR_ROLE_BACKWARD_X], w, dy, dx, workspace, s);
         if (st != FBCORR_OK) return st;

@@ -25,6 +25,10 @@ struct Plan {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[FBCORR_ROLE_COUNT];
     double acc_ms[FBCORR_ROLE_COUNT] = {0, 0, 0};
     int64_t acc_calls[FBCORR_ROLE_COUNT] = {0, 0, 0};
+    // backward: dW runs on a side stream forked from and joined back into
+    // the caller's stream, concurrently with dX
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // many uneven images
     bool batched = false;
     size_t batch_ws = 0;

@@ -69,6 +69,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #define GPER ((GITEMS + NTHREADS - 1) / NTHREADS)
 #define XPER ((XITEMS + NTHREADS - 1) / NTHREADS)
 
+// A wave's tiles are NW apart in the row-fastest numbering, so they all lie
+// in one filter-row tile when NW is a multiple of the row-tile count; the A
+// fragment is then read once per step.  (If a wave's first tile is past the
+// end, so are all its others.)
+#define SAMEROW (NW % NROWT == 0)
+
 static_assert(PC % 2 == 0, "pixel chunk must be even");
 
 extern "C" __global__ void __launch_bounds__(NTHREADS)
@@ -167,9 +173,16 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
         for (int t = 0; t < PC / 2; ++t) {
             const int p = h * (PC / 2) + t;
             const int xo = (p / RW) * XRS + (p % RW) * D;
+#if SAMEROW
+            const float a0 = gl[p * GST + arow[0]];
+#endif
 #pragma unroll
             for (int k = 0; k < TPW; ++k) {
+#if SAMEROW
+                const float a = a0;
+#else
                 const float a = gl[p * GST + arow[k]];
+#endif
                 const float bb = xl[xo + qoff[k]];
                 acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
             }
