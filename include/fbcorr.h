@@ -192,7 +192,11 @@ FBCORR_API fbcorr_status fbcorr_plan_batched(int32_t count, const fbcorr_desc* d
  * into a HIP graph on the first call per stream (which must be a created
  * stream, not the null stream) and replays it afterwards;
  * the pointer arrays are then read at replay time, so their contents may
- * change between calls but their addresses and the workspace must not. */
+ * change between calls but their addresses and the workspace must not.
+ * The plan's work table lives in the workspace: it is written on the first
+ * call with a given workspace address (synchronously), so that memory must
+ * not be reused for anything else while the plan uses it.  Calls from
+ * several threads are serialised inside the plan. */
 FBCORR_API fbcorr_status fbcorr_forward_batched(fbcorr_plan_t plan, const float* const* xs,
                                      const float* const* ws_, float* const* ys,
                                      void* workspace, size_t workspace_bytes, void* stream,

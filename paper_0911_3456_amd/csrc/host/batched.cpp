@@ -50,6 +50,7 @@ struct BatchedState {
         }
     };
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    std::mutex mu;           // uploads and graphs are shared by calling threads
 };
 
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -474,6 +475,7 @@ extern "C" fbcorr_status fbcorr_forward_batched(fbcorr_plan_t plan, const float*
         if (r != FBCORR_OK) return r;
         DeviceGuard g(p->device);
         hipStream_t s = (hipStream_t)stream;
+        std::lock_guard<std::mutex> lock(st->mu);
         if (!st->uploaded.count(workspace)) {
             // the work table and image table live in the caller's workspace
             char* base = (char*)workspace;

@@ -187,7 +187,8 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     const int threads = wm * wn * ksp * 64;
     if (threads > std::min(1024, di.max_threads)) { err = "igemm: too many threads"; return false; }
     const int nreg = mf * mf / 64;
-    if (mt * nt * nreg > 128) { err = "igemm: more than 128 accumulator registers per lane"; return false; }
+    // accumulators live in the AGPR half of the register file: at most 256
+    if (mt * nt * nreg > 256) { err = "igemm: more than 256 accumulator registers per lane"; return false; }
     const int ncol = wn * nt * mf;
     if (ncol % s) { err = "igemm: columns must split evenly into shifts"; return false; }
     const int cb = ncol / s;

@@ -313,7 +313,9 @@ fbcorr_status fbcorr_backward(fbcorr_plan_t plan, const float* x, const float* w
         // The two gradients are independent: dW goes to a side stream forked
         // from the caller's stream and joined back, so the tail of one
         // kernel overlaps the other.  (Default-priority stream; the event
-        // pair also works under graph capture.)
+        // pair also works under graph capture.)  Calls from several threads
+        // enqueue their fork/join sequences one at a time.
+        std::lock_guard<std::mutex> side_lock(p->side_mu);
         if (!p->side) {
             hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);

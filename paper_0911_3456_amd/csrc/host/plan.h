@@ -29,6 +29,7 @@ struct Plan {
     // the caller's stream, concurrently with dX
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex side_mu;      // one fork/launch/join sequence at a time
     // many uneven images
     bool batched = false;
     size_t batch_ws = 0;

@@ -73,7 +73,8 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         // (mt, nt, wm, wn): per-wave tiles and waves per contraction group
         const int shapes[][4] = {{1, 1, 4, 1}, {1, 2, 4, 1}, {2, 1, 2, 2}, {2, 2, 2, 1}, {1, 2, 2, 2},
                                  {2, 2, 4, 1}, {1, 4, 4, 1}, {2, 2, 2, 2}, {4, 2, 1, 1}, {1, 1, 8, 1},
-                                 {1, 1, 1, 1}, {2, 1, 1, 1}, {1, 2, 1, 1}, {2, 2, 1, 1}, {1, 1, 2, 1}};
+                                 {1, 1, 1, 1}, {2, 1, 1, 1}, {1, 2, 1, 1}, {2, 2, 1, 1}, {1, 1, 2, 1},
+                                 {2, 4, 2, 1}, {4, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {2, 4, 4, 1}};
         std::vector<Config> grid;
         for (int kc : kcs)
             for (int s : ss)
@@ -93,7 +94,8 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                     // skip tiles whose columns exceed what the channels can fill
                                     const int cs = c.v["s"];
                                     if (sh[1] * sh[3] * mf > std::max(mf, ((cout * cs + mf - 1) / mf) * mf)) continue;
-                                    if (sh[0] * sh[1] * sh[2] * sh[3] * ksp > 16) continue;
+                                    if (sh[0] * sh[1] * sh[2] * sh[3] * ksp > 32) continue;
+                                    if (sh[0] * sh[1] > 8 && !lp) continue;   // big wave tiles pay off for 16-bit
                                     c.v["ustage"] = us;
                                     // LDS row padding (bank-conflict avoidance), in whole vectors
                                     const int unit = lp ? 8 : 4;
