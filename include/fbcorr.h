@@ -39,7 +39,8 @@
  *    calling thread's fbcorr_last_error() then holds a message.  After any
  *    status other than FBCORR_ERR_LAUNCH the plan stays usable.
  *  - A plan may be used from several threads at once on different streams
- *    with separate workspaces, except during fbcorr_tune.
+ *    with separate workspaces, except during fbcorr_tune,
+ *    fbcorr_plan_set_config and fbcorr_plan_set_epilogue.
  */
 #ifndef FBCORR_H
 #define FBCORR_H
@@ -211,6 +212,17 @@ FBCORR_API fbcorr_status fbcorr_plan_get_config(fbcorr_plan_t plan, int role, ch
  * (keys not given keep their defaults).  Compiles it; on any error the
  * previous configuration stays in place. */
 FBCORR_API fbcorr_status fbcorr_plan_set_config(fbcorr_plan_t plan, int role, const char* cfg);
+
+/* Fused elementwise epilogue for the forward pass (the static nonlinearity
+ * that follows each filtering layer in the vision model family of Sec. 6.2,
+ * Fig. 5b), generated into the forward kernel's store like the paper's
+ * elementwise kernels (Sec. 5.2, Fig. 4): `expr` is a single-line C
+ * expression of `v` (the float output value) and `c` (its filter index),
+ * e.g. "fminf(fmaxf(v, 0.f), 1.f)".  NULL or "" removes it.  The forward
+ * kernel is recompiled; a compile error leaves the previous kernel in place
+ * (FBCORR_ERR_COMPILE with the log).  Plans with an epilogue have no
+ * backward pass (FBCORR_ERR_UNSUPPORTED). */
+FBCORR_API fbcorr_status fbcorr_plan_set_epilogue(fbcorr_plan_t plan, const char* expr);
 
 /* Kernel timing: when enabled, the library records HIP events around the
  * main kernel of each role on the caller's stream and accumulates the

@@ -30,7 +30,7 @@ ROLES = {"forward": 0, "backward_x": 1, "backward_w": 2}
 EXPORTS = (
     "fbcorr_plan", "fbcorr_plan_destroy", "fbcorr_workspace_size", "fbcorr_forward",
     "fbcorr_backward", "fbcorr_tune", "fbcorr_plan_batched", "fbcorr_forward_batched",
-    "fbcorr_plan_get_config", "fbcorr_plan_set_config", "fbcorr_plan_enable_timing",
+    "fbcorr_plan_get_config", "fbcorr_plan_set_config", "fbcorr_plan_set_epilogue", "fbcorr_plan_enable_timing",
     "fbcorr_plan_read_timing", "fbcorr_codegen", "fbcorr_compile_check", "fbcorr_compile_check_batched",
     "fbcorr_cache_stats", "fbcorr_cache_clear",
     "fbcorr_last_error", "fbcorr_status_string", "fbcorr_version",
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fbcorr_forward_batched.argtypes = [P, P, P, P, P, sz, P, ctypes.c_int]
     lib.fbcorr_plan_get_config.argtypes = [P, ctypes.c_int, ctypes.c_char_p, sz]
     lib.fbcorr_plan_set_config.argtypes = [P, ctypes.c_int, ctypes.c_char_p]
+    lib.fbcorr_plan_set_epilogue.argtypes = [P, ctypes.c_char_p]
     lib.fbcorr_plan_enable_timing.argtypes = [P, ctypes.c_int]
     lib.fbcorr_plan_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int]

@@ -41,6 +41,8 @@ fbcorr_status compile_role(Plan* p, int role, const Config& c) {
         set_error(FBCORR_ERR_UNSUPPORTED, err);
         return FBCORR_ERR_UNSUPPORTED;
     }
+    if (role == FBCORR_ROLE_FORWARD && !p->epilogue.empty())
+        rb.main.options.push_back("-DFB_EPILOGUE(v,c)=(" + p->epilogue + ")");
     RoleExec ex;
     fbcorr_status st = load_kernel(rb.main, p->device, ex.main);
     if (st != FBCORR_OK) return st;
@@ -303,6 +305,8 @@ fbcorr_status fbcorr_backward(fbcorr_plan_t plan, const float* x, const float* w
     if (dx && ((st = check_ptr(w, "w")) || (st = check_ptr(dx, "dx")))) return st;
     if (dw && ((st = check_ptr(x, "x")) || (st = check_ptr(dw, "dw")))) return st;
     if (!dx && !dw) return FBCORR_OK;
+    FBC_RETURN_IF(!p->epilogue.empty(), FBCORR_ERR_UNSUPPORTED,
+                  "the backward pass of a plan with a fused epilogue is not provided");
     DeviceGuard g(p->device);
     if ((st = ensure_role(p, FBCORR_ROLE_BACKWARD_X)) || (st = ensure_role(p, FBCORR_ROLE_BACKWARD_W))) return st;
     size_t off_w = 0;
@@ -387,6 +391,29 @@ fbcorr_status fbcorr_plan_set_config(fbcorr_plan_t plan, int role, const char* c
         return FBCORR_ERR_INVALID_ARGUMENT;
     }
     return compile_role(p, role, c);
+    FBC_API_END
+}
+
+fbcorr_status fbcorr_plan_set_epilogue(fbcorr_plan_t plan, const char* expr) {
+    FBC_API_BEGIN
+    clear_error();
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    FBC_RETURN_IF(!p, FBCORR_ERR_INVALID_ARGUMENT, "plan is NULL");
+    FBC_RETURN_IF(p->batched, FBCORR_ERR_UNSUPPORTED, "batched plans have no epilogue");
+    const std::string e = expr ? expr : "";
+    FBC_RETURN_IF(e.size() > 1024, FBCORR_ERR_INVALID_ARGUMENT, "epilogue longer than 1024 characters");
+    for (char ch : e)
+        FBC_RETURN_IF(ch == '\n' || ch == '\r' || ch == '#' || ch == '\\', FBCORR_ERR_INVALID_ARGUMENT,
+                      "epilogue must be a single-line expression (no '#', '\\' or line breaks)");
+    DeviceGuard g(p->device);
+    const std::string prev = p->epilogue;
+    p->epilogue = e;
+    fbcorr_status st = compile_role(p, FBCORR_ROLE_FORWARD, p->role[FBCORR_ROLE_FORWARD].build.cfg);
+    if (st != FBCORR_OK) {
+        p->epilogue = prev;     // the previous kernel stays installed
+        return st;
+    }
+    return FBCORR_OK;
     FBC_API_END
 }
 

@@ -25,6 +25,8 @@ struct Plan {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[FBCORR_ROLE_COUNT];
     double acc_ms[FBCORR_ROLE_COUNT] = {0, 0, 0};
     int64_t acc_calls[FBCORR_ROLE_COUNT] = {0, 0, 0};
+    // fused forward epilogue (empty: none)
+    std::string epilogue;
     // backward: dW runs on a side stream forked from and joined back into
     // the caller's stream, concurrently with dX
     hipStream_t side = nullptr;

@@ -21,6 +21,8 @@
 //            LAYOUT (0: tile [row][col][d], 1: tile [d][row][col])
 //            XPAD WPAD (LDS padding)  UD (unroll of the channel loop)
 //            XCDMAP (XCD-aware workgroup order)
+//   EPILOGUE(v, c)  optional elementwise function of an output value v and
+//            its filter c, applied before the store (a fused nonlinearity)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -196,7 +198,13 @@ fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* _
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     const int n = n0 + fg * Q + q;
-                    if ((q % DS) == ds && n < N) y[(yb + oj) * N + n] = acc[p][q];
+                    if ((q % DS) == ds && n < N) {
+#ifdef FB_EPILOGUE
+                        y[(yb + oj) * N + n] = FB_EPILOGUE(acc[p][q], n);   // fused elementwise epilogue
+#else
+                        y[(yb + oj) * N + n] = acc[p][q];
+#endif
+                    }
                 }
             }
         }

@@ -3,7 +3,8 @@
 //   fbcorr_sum_partials  out[i] = sum_{p<NP} part[p*L + i]; slice k < RS adds
 //                        p = k, k+RS, k+2RS, ... in increasing order, then the
 //                        RS slice sums are added in increasing k (a fixed
-//                        order, so the result is deterministic).
+//                        order, so the result is deterministic); four
+//                        consecutive i per thread when L % 4 == 0.
 //   fbcorr_flip_filters  wf[d,u,v,n] = w[n, FH-1-u, FW-1-v, d]: the filters of
 //                        the input-gradient correlation.
 //   fbcorr_pack_lowp     per filter n: e_n = floor(log2 max|w[n]|),
@@ -44,24 +45,47 @@
 #endif
 
 #ifdef FB_SUM_PARTIALS
+// Four consecutive outputs per thread when L allows 16-byte loads.
+#define SV ((L % 4 == 0) ? 4 : 1)
+#define LV (L / SV)
+typedef float f32x4s __attribute__((ext_vector_type(4)));
 extern "C" __global__ void __launch_bounds__(64 * RS)
 fbcorr_sum_partials(const float* __restrict__ part, float* __restrict__ out)
 {
-    __shared__ float red[RS][64];
+    __shared__ float red[RS][64 * SV];
     const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const long i = (long)blockIdx.x * 64 + e;
-    float s = 0.f;
-    if (i < L) {
-        for (int p = sl; p < NP; p += RS) s += part[(long)p * L + i];
+    const long i = (long)blockIdx.x * 64 + e;        // in units of SV floats
+#if SV == 4
+    f32x4s acc = {0.f, 0.f, 0.f, 0.f};
+    if (i < LV) {
+        for (int p = sl; p < NP; p += RS) acc += *(const f32x4s*)(part + (long)p * L + i * 4);
     }
-    red[sl][e] = s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[sl][e * 4 + k] = acc[k];
     __syncthreads();
-    if (sl == 0 && i < L) {
+    if (sl == 0 && i < LV) {
+        f32x4s t = {red[0][e * 4], red[0][e * 4 + 1], red[0][e * 4 + 2], red[0][e * 4 + 3]};
+#pragma unroll
+        for (int k = 1; k < RS; ++k) {
+            t[0] += red[k][e * 4]; t[1] += red[k][e * 4 + 1];
+            t[2] += red[k][e * 4 + 2]; t[3] += red[k][e * 4 + 3];
+        }
+        *(f32x4s*)(out + i * 4) = t;
+    }
+#else
+    float acc = 0.f;
+    if (i < LV) {
+        for (int p = sl; p < NP; p += RS) acc += part[(long)p * L + i];
+    }
+    red[sl][e] = acc;
+    __syncthreads();
+    if (sl == 0 && i < LV) {
         float t = red[0][e];
 #pragma unroll
         for (int k = 1; k < RS; ++k) t += red[k][e];
         out[i] = t;
     }
+#endif
 }
 #endif
 

@@ -140,6 +140,11 @@ class Plan:
     def set_config(self, role: str, cfg: str) -> None:
         nat.check(self.lib.fbcorr_plan_set_config(self.handle, nat.ROLES[role], cfg.encode()))
 
+    def set_epilogue(self, expr: str | None) -> None:
+        """Fuse an elementwise C expression of v (value) and c (filter) into
+        the forward kernel's store; None removes it."""
+        nat.check(self.lib.fbcorr_plan_set_epilogue(self.handle, expr.encode() if expr else None))
+
     def enable_timing(self, on=True) -> None:
         nat.check(self.lib.fbcorr_plan_enable_timing(self.handle, 1 if on else 0))
 

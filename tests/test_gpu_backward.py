@@ -219,3 +219,49 @@ def test_differentiation_workload():
         _, rw = oracle.backward(x, w[n:n + 1], g[..., n:n + 1], want_dx=False)
         _, sw = oracle.backward(np.abs(x), np.abs(w[n:n + 1]), np.abs(g[..., n:n + 1]), want_dx=False)
         assert oracle.normalised_error(dw[n:n + 1], rw, sw)[0] <= TOL
+
+
+def test_concurrent_backward_from_two_threads():
+    """One plan used from two host threads on two streams with separate
+    workspaces (the documented concurrency contract): both results exact."""
+    need_gpu()
+    import threading
+    import torch
+    from paper_0911_3456_amd import Plan
+    s = wl.Shape(2, 60, 70, 8, 64, 7, 7)
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw)
+    need = plan.workspace_size(1)
+    data, refs, outs = [], [], [None, None]
+    for t in range(2):
+        x, w, rng = wl.draw_integer(s, seed=50 + t, xmax=3, wmax=3)
+        g = rng.integers(-3, 4, size=(s.batch, s.Ho, s.Wo, s.N)).astype(np.float32)
+        data.append(to_dev(x, w, g))
+        refs.append(oracle.backward(x, w, g))
+    import ctypes
+    from paper_0911_3456_amd import _native as nat
+
+    def worker(t):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            xt, wt, gt = data[t]
+            ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+            wsp = ws.data_ptr() + (-ws.data_ptr()) % 256
+            dx, dw = torch.empty_like(xt), torch.empty_like(wt)
+            for _ in range(5):
+                nat.check(plan.lib.fbcorr_backward(plan.handle, ctypes.c_void_p(xt.data_ptr()),
+                                                   ctypes.c_void_p(wt.data_ptr()), ctypes.c_void_p(gt.data_ptr()),
+                                                   ctypes.c_void_p(dx.data_ptr()), ctypes.c_void_p(dw.data_ptr()),
+                                                   ctypes.c_void_p(wsp), need,
+                                                   ctypes.c_void_p(stream.cuda_stream)))
+            stream.synchronize()
+            outs[t] = (dx.cpu().numpy(), dw.cpu().numpy())
+
+    torch.cuda.synchronize()
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for t in range(2):
+        np.testing.assert_array_equal(outs[t][0], refs[t][0].astype(np.float32))
+        np.testing.assert_array_equal(outs[t][1], refs[t][1].astype(np.float32))
