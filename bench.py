@@ -259,7 +259,7 @@ def paper_table(reps: int):
     import workloads as wl
     from paper_0911_3456_amd import Plan
     dev = torch.device("cuda", 0)
-    rows = []
+    rows, kept = [], []
     for H, W, D, N, fh, fw in PAPER_SHAPES:
         s = wl.Shape(1, H, W, D, N, fh, fw)
         x, w, _ = wl.draw_single(s, seed=6)
@@ -280,8 +280,39 @@ def paper_table(reps: int):
         row["candidates"] = {"direct": rep["n_compiled"], "igemm": rep2["n_compiled"]}
         print(json.dumps(row), flush=True)
         rows.append(row)
-        pd.close()
+        kept.append((s, pd, xt, wt, y, rep["best_cfg"]))
         pi.close()
+    # Per-input optimum: each shape run with every other shape's tuned direct
+    # configuration (the paper reports that the best variant differs per input
+    # and per GPU).  penalty = time(foreign) / time(own) - 1; null where the
+    # foreign configuration does not fit this shape.
+    def fwd_ms(pd, xt, wt, y):
+        for _ in range(2):
+            pd.forward(xt, wt, y)
+        pd.enable_timing(True)
+        pd.read_timing(reset=True)
+        for _ in range(reps):
+            pd.forward(xt, wt, y)
+        ms, calls = pd.read_timing(reset=True)["forward"]
+        pd.enable_timing(False)
+        return ms / max(calls, 1)
+    own = [fwd_ms(pd, xt, wt, y) for _, pd, xt, wt, y, _ in kept]
+    for a, (s, pd, xt, wt, y, cfg) in enumerate(kept):
+        pen = {}
+        for b, other in enumerate(kept):
+            if a == b:
+                continue
+            try:
+                pd.set_config("forward", other[5])
+                pen[rows[b]["input"] + "/" + rows[b]["filter_bank"]] = round(fwd_ms(pd, xt, wt, y) / own[a] - 1, 4)
+            except Exception:
+                pen[rows[b]["input"] + "/" + rows[b]["filter_bank"]] = None
+        pd.set_config("forward", cfg)
+        rows[a]["foreign_optimum_penalty"] = pen
+        print(json.dumps({"input": rows[a]["input"], "filter_bank": rows[a]["filter_bank"],
+                          "foreign_optimum_penalty": pen}), flush=True)
+    for k in kept:
+        k[1].close()
     return rows
 
 

@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the filter-bank correlation (test infrastructure).
+"""CPU oracles for the filter-bank correlation and the exact nearest-neighbour
+search (test infrastructure).
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
 the benchmark's CPU-baseline leg may import this package.  The GPU library
@@ -12,7 +13,11 @@ stride one, no flip (readings recorded in the design notes).  The arithmetic
 is the plain definition written out in ``fbcorr_oracle.c`` and run in double
 precision on the exact float32 input values.
 
-Besides the three loops this module holds the oracle-side helpers the tests
+The second oracle, ``nearest_oracle.c`` (Sec. 6.4, the natural-image entropy
+application), is exhaustive exact nearest-neighbour search over 8-bit patches
+in 64-bit integers, lowest index on ties.
+
+Besides the loops this module holds the oracle-side helpers the tests
 need: the normalised error metric, round-to-nearest-even casts to bfloat16
 and float16 (for an oracle on rounded operands), per-filter power-of-two
 scales, and windowed central finite differences of L = sum(g * y).
@@ -27,7 +32,7 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fbcorr_oracle.c")
+_SRCS = [os.path.join(_HERE, "fbcorr_oracle.c"), os.path.join(_HERE, "nearest_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -35,10 +40,10 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-o", tmp, _SRC])
+                               "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -54,6 +59,8 @@ def _load():
             lib.fbo_forward.argtypes = [dp, dp, dp] + [i64] * 7
             lib.fbo_backward_x.argtypes = [dp, dp, dp] + [i64] * 7
             lib.fbo_backward_w.argtypes = [dp, dp, dp] + [i64] * 7
+            lib.nno_search.argtypes = [ctypes.c_void_p, ctypes.c_void_p, i64, i64, i64,
+                                       ctypes.c_void_p, ctypes.c_void_p]
             lib.fbo_set_threads.argtypes = [ctypes.c_int]
             lib.fbo_max_threads.restype = ctypes.c_int
             _lib = lib
@@ -118,6 +125,23 @@ def backward(x: np.ndarray, w: np.ndarray, g: np.ndarray, want_dx=True, want_dw=
         dw = np.empty_like(w)
         lib.fbo_backward_w(_p(x), _p(g), _p(dw), B, H, W, D, N, fh, fw)
     return dx, dw
+
+
+def nearest(targets: np.ndarray, neighbors: np.ndarray):
+    """Exact nearest neighbour of every target row among the neighbour rows
+    (Sec. 6.4): returns (idx, dist) as int64 arrays, dist the squared
+    Euclidean distance, idx the lowest index at that distance."""
+    t = np.ascontiguousarray(targets, dtype=np.uint8)
+    n = np.ascontiguousarray(neighbors, dtype=np.uint8)
+    if t.ndim != 2 or n.ndim != 2 or t.shape[1] != n.shape[1]:
+        raise ValueError("targets [T, D] and neighbors [M, D] with the same D")
+    if n.shape[0] == 0:
+        raise ValueError("empty neighbour set")
+    idx = np.empty(t.shape[0], np.int64)
+    dist = np.empty(t.shape[0], np.int64)
+    _load().nno_search(t.ctypes.data, n.ctypes.data, t.shape[0], n.shape[0], t.shape[1],
+                       idx.ctypes.data, dist.ctypes.data)
+    return idx, dist
 
 
 # --------------------------------------------------------------------------

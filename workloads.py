@@ -171,3 +171,64 @@ def fd_coordinates(shape: Shape, rng: np.random.Generator, nx: int = 100, nw: in
     cw = np.stack([rng.integers(0, shape.N, nw), rng.integers(0, shape.fh, nw),
                    rng.integers(0, shape.fw, nw), rng.integers(0, shape.D, nw)], axis=1)
     return cx, cw
+
+
+# --------------------------------------------------------------------------
+# Nearest-neighbour search over image patches (Sec. 6.4 and its table of
+# search times: 4096 target patches of 8 x 8 pixels, neighbour sets of 4096
+# to 1,048,576 patches).  The natural-image database that application used
+# is not available here, so synthetic images with the best-known statistic of
+# natural scenes stand in: an amplitude spectrum falling as 1/f (power 1/f^2)
+# with random phases, scaled to mean 128 and standard deviation 48, clipped
+# to [0, 255] and rounded to 8-bit pixels.  Patches are cut at distinct
+# random positions (without replacement inside an image); targets come from
+# images of their own, disjoint from the neighbours' images.
+# --------------------------------------------------------------------------
+
+NN_TARGETS = 4096
+NN_NEIGHBOURS = (4096, 16384, 65536, 262144, 1048576)
+NN_PATCH = 8
+NN_IMAGE_SIDE = 512
+NN_PER_IMAGE = 16384
+
+
+def draw_images(count: int, rng: np.random.Generator, side: int = NN_IMAGE_SIDE) -> np.ndarray:
+    """count images side x side of 8-bit pixels with a 1/f amplitude spectrum."""
+    fy = np.fft.fftfreq(side)[:, None]
+    fx = np.fft.rfftfreq(side)[None, :]
+    f = np.sqrt(fx * fx + fy * fy)
+    f[0, 0] = 1.0
+    out = np.empty((count, side, side), np.uint8)
+    for k in range(count):
+        spec = np.fft.rfft2(rng.standard_normal((side, side))) / f
+        spec[0, 0] = 0.0
+        img = np.fft.irfft2(spec, s=(side, side))
+        img = 128.0 + 48.0 * (img - img.mean()) / img.std()
+        out[k] = np.clip(np.rint(img), 0, 255).astype(np.uint8)
+    return out
+
+
+def draw_patches(count: int, seed: int, patch: int = NN_PATCH, per_image: int = NN_PER_IMAGE,
+                 side: int = NN_IMAGE_SIDE) -> np.ndarray:
+    """count patches [count, patch*patch] (uint8, row-major pixels) cut from
+    ceil(count / per_image) synthetic images at distinct positions."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((count, patch * patch), np.uint8)
+    npos = side - patch + 1
+    done = 0
+    while done < count:
+        img = draw_images(1, rng, side)[0]
+        take = min(per_image, count - done)
+        pos = rng.choice(npos * npos, size=take, replace=False)
+        ii, jj = pos // npos, pos % npos
+        win = np.lib.stride_tricks.sliding_window_view(img, (patch, patch))
+        out[done:done + take] = win[ii, jj].reshape(take, patch * patch)
+        done += take
+    return out
+
+
+def draw_nn(n_targets: int, n_neighbours: int, seed: int = 7, patch: int = NN_PATCH):
+    """Targets and neighbours for one search (separate image draws)."""
+    targets = draw_patches(n_targets, seed * 1000 + 1, patch)
+    neighbours = draw_patches(n_neighbours, seed * 1000 + 2, patch)
+    return targets, neighbours
