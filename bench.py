@@ -20,6 +20,11 @@ Also printed in the same JSON line:
   differentiation  32 inputs 128x128x16, 64 filters 7x7x16, forward + dX + dW.
   batched       256 uneven images with their own banks in one persistent
                 launch, replayed from a HIP graph.
+  nearest_neighbour  exact brute-force nearest-neighbour search of 4096
+                8x8-pixel target patches against 4096 ... 1,048,576
+                neighbours (the sizes of the paper's search-time table,
+                Sec. 6.4), with the paper's GTX 295 times for context; the
+                int8 matrix-core scan kernel against the int8 peak.
 """
 from __future__ import annotations
 
@@ -36,6 +41,11 @@ sys.path.insert(0, ROOT)
 FP32_MATRIX_PEAK_TFLOPS = 157.3     # MI355X dense fp32 matrix (and packed-vector) peak
 FP32_VALU_PEAK_TFLOPS = 78.6        # 256 CU * 64 FMA/clk * 2 flop * 2.4 GHz, no packed fp32
 BF16_MATRIX_PEAK_TFLOPS = 2500.0
+INT8_MATRIX_PEAK_TOPS = 5000.0
+# Search times of the paper's nearest-neighbour table (Sec. 6.4), seconds:
+# one GPU of a GTX 295, and one core of a 2.4 GHz Core2 (C, gcc -O).
+PAPER_NN_GTX295_S = {4096: 0.089, 16384: 0.299, 65536: 1.146, 262144: 4.508, 1048576: 17.989}
+PAPER_NN_CPU_S = {4096: 3.76, 16384: 15.03, 65536: 60.16, 262144: 242.13, 1048576: 969.00}
 ROLES = ("forward", "backward_x", "backward_w")
 
 
@@ -48,6 +58,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-nn", action="store_true")
     ap.add_argument("--paper-table", action="store_true",
                     help="default vs auto-tuned forward on the paper's four table shapes, then exit")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -250,6 +261,50 @@ PAPER_SHAPES = [  # (H, W, D, N, fh, fw): the four shapes of the paper's fbconv3
     (256, 256, 8, 64, 9, 9), (512, 512, 4, 32, 13, 13), (1024, 1024, 8, 16, 5, 5), (2048, 2048, 4, 4, 8, 8)]
 
 
+def nn_leg(steps: int, warmup: int):
+    """Exact nearest-neighbour search at every neighbour-set size of the
+    paper's table; the largest carries the scan kernel's roofline."""
+    import torch
+    import workloads as wl
+    from paper_0911_3456_amd import NNPlan
+    dev = torch.device("cuda", 0)
+    T, D = wl.NN_TARGETS, wl.NN_PATCH * wl.NN_PATCH
+    t, n = wl.draw_nn(T, wl.NN_NEIGHBOURS[-1], seed=7)
+    tt, nt = torch.from_numpy(t).to(dev), torch.from_numpy(n).to(dev)
+    rows = []
+    for m in wl.NN_NEIGHBOURS:
+        plan = NNPlan(T, m, D, device=dev)
+        nm = nt[:m]
+        idx, dist = plan.search(tt, nm)
+        reps = max(3, steps // 5) if m < wl.NN_NEIGHBOURS[-1] else max(3, steps // 2)
+        for _ in range(warmup):
+            plan.search(tt, nm, idx, dist)
+        torch.cuda.synchronize()
+        plan.read_timing(reset=True)
+        plan.enable_timing(True)
+        sec = time_steps(lambda: plan.search(tt, nm, idx, dist), reps, 0)
+        plan.enable_timing(False)
+        tm = plan.read_timing(reset=True)
+        k = {name: v[0] / max(v[1], 1) for name, v in tm.items()}
+        ops = 2 * T * m * D
+        row = {"neighbours": m, "ms": round(sec * 1e3, 4), "gops": round(ops / sec / 1e9, 1),
+               "kernel_ms": {name: round(v, 4) for name, v in k.items()},
+               "scan_tops": round(ops / (k["scan"] * 1e-3) / 1e12, 2),
+               "paper_gtx295_s": PAPER_NN_GTX295_S[m], "speedup_vs_paper_gtx295": round(
+                   PAPER_NN_GTX295_S[m] / sec, 1), "config": plan.get_config()}
+        rows.append(row)
+        log("nn", m, row["ms"], "ms", row["scan_tops"], "TOP/s scan")
+        plan.close()
+    big = rows[-1]
+    achieved = big["scan_tops"]
+    return {"workload": "4096 target patches 8x8 (uint8) against 4096 ... 1,048,576 neighbours, exact",
+            "ops_per_search": "2 * T * M * D (one multiply and one add per pixel pair)",
+            "rows": rows,
+            "roofline": {"bound": "mfma", "kernel": "fbnn_scan", "achieved": achieved,
+                         "peak": INT8_MATRIX_PEAK_TOPS, "unit": "TOP/s",
+                         "frac": round(achieved / INT8_MATRIX_PEAK_TOPS, 4), "traffic": None}}
+
+
 def paper_table(reps: int):
     """The paper's experiment on this GPU: per table shape, the hand-written
     default direct kernel vs the auto-tuned direct kernel ("boost"), and the
@@ -422,6 +477,9 @@ def main():
     if not args.no_batched and args.only == "step":
         log("batched leg ...")
         result["batched"] = batched_leg(args.steps, args.warmup)
+    if not args.no_nn and args.only == "step":
+        log("nearest-neighbour leg ...")
+        result["nearest_neighbour"] = nn_leg(args.steps, args.warmup)
     if not args.no_cpu_baseline and args.only == "step":
         log("cpu baseline (FP64 oracle) ...")
         result["cpu_baseline"] = cpu_baseline(s, x, w, g)

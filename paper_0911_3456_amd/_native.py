@@ -1,4 +1,4 @@
-"""ctypes binding of the fbcorr C ABI (``include/fbcorr.h``).
+"""ctypes binding of the fbcorr C ABI (``include/fbcorr.h``, ``include/fbnn.h``).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``libfbcorr.so``.  torch is imported first so that the library's
@@ -35,6 +35,17 @@ EXPORTS = (
     "fbcorr_cache_stats", "fbcorr_cache_clear",
     "fbcorr_last_error", "fbcorr_status_string", "fbcorr_version",
 )
+# Every entry point declared in include/fbnn.h.
+NN_EXPORTS = (
+    "fbnn_plan", "fbnn_plan_destroy", "fbnn_workspace_size", "fbnn_search", "fbnn_tune",
+    "fbnn_plan_get_config", "fbnn_plan_set_config", "fbnn_plan_enable_timing", "fbnn_plan_read_timing",
+    "fbnn_compile_check",
+)
+
+
+class NNDesc(ctypes.Structure):
+    _fields_ = [("n_targets", ctypes.c_int64), ("n_neighbors", ctypes.c_int64), ("dim", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
 
 class Desc(ctypes.Structure):
@@ -110,6 +121,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fbcorr_status_string.restype = ctypes.c_char_p
     lib.fbcorr_status_string.argtypes = [ctypes.c_int]
     lib.fbcorr_version.restype = ctypes.c_int
+    lib.fbnn_plan.argtypes = [ctypes.POINTER(NNDesc), ctypes.c_int, ctypes.POINTER(P)]
+    lib.fbnn_plan_destroy.argtypes = [P]
+    lib.fbnn_workspace_size.argtypes = [P, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.fbnn_search.argtypes = [P, P, P, P, P, P, sz, P]
+    lib.fbnn_tune.argtypes = [P, P, P, P, sz, P, ctypes.POINTER(TuneOpts), ctypes.POINTER(TuneReport)]
+    lib.fbnn_plan_get_config.argtypes = [P, ctypes.c_char_p, sz]
+    lib.fbnn_plan_set_config.argtypes = [P, ctypes.c_char_p]
+    lib.fbnn_plan_enable_timing.argtypes = [P, ctypes.c_int]
+    lib.fbnn_plan_read_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.c_int]
+    lib.fbnn_compile_check.argtypes = [ctypes.POINTER(NNDesc), ctypes.c_char_p, ctypes.c_char_p,
+                                       ctypes.POINTER(sz)]
+    for name in NN_EXPORTS:
+        getattr(lib, name).restype = st
     for name in EXPORTS:
         if name not in ("fbcorr_last_error", "fbcorr_status_string", "fbcorr_version"):
             getattr(lib, name).restype = st
@@ -154,6 +179,16 @@ def compile_check_batched(descs, arch: str = "gfx950") -> int:
     arr = (Desc * len(descs))(*descs)
     n = ctypes.c_size_t(0)
     check(lib.fbcorr_compile_check_batched(len(descs), arr, arch.encode(), ctypes.byref(n)))
+    return n.value
+
+
+def nn_compile_check(n_targets: int, n_neighbors: int, dim: int, cfg: str | None = None,
+                     arch: str = "gfx950") -> int:
+    """Compile the nearest-neighbour kernels with hiprtc without a device."""
+    lib = load()
+    n = ctypes.c_size_t(0)
+    d = NNDesc(n_targets, n_neighbors, dim, 0)
+    check(lib.fbnn_compile_check(ctypes.byref(d), cfg.encode() if cfg else None, arch.encode(), ctypes.byref(n)))
     return n.value
 
 

@@ -34,7 +34,10 @@ bool parse_config(const std::string& text, Config& base, std::string& err) {
         if (eq == std::string::npos || eq == 0) { err = "bad token '" + tok + "'"; return false; }
         std::string k = tok.substr(0, eq), val = tok.substr(eq + 1);
         if (k == "algo") {
-            if (val != "igemm" && val != "direct" && val != "dw") { err = "unknown algo '" + val + "'"; return false; }
+            if (val != "igemm" && val != "direct" && val != "dw" && val != "nn") {
+                err = "unknown algo '" + val + "'";
+                return false;
+            }
             if (val != c.algo) {
                 c.algo = val;
                 c.v.clear();          // keys of another algorithm do not carry over

@@ -37,6 +37,8 @@ bool tuning_db_lookup(const std::string& arch, int role, const fbcorr_desc& d, s
 bool tuning_db_record(const std::string& arch, int role, const fbcorr_desc& d, const std::string& cfg,
                       std::string& err);
 void tuning_db_reload();
+bool tuning_db_lookup_key(const std::string& key, std::string& cfg);
+bool tuning_db_record_key(const std::string& key, const std::string& cfg, std::string& err);
 Config default_igemm(int cin, int cout, bool lowp);
 Config default_direct(const fbcorr_desc& d);
 bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,

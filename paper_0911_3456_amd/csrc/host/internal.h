@@ -32,11 +32,24 @@ void clear_error();
         }                                         \
     } while (0)
 
+// C ABI entry points turn exceptions into FBCORR_ERR_INTERNAL.
+#define FBC_API_BEGIN try {
+#define FBC_API_END                                                            \
+    }                                                                          \
+    catch (const std::exception& e) {                                          \
+        ::fbc::set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what()); \
+        return FBCORR_ERR_INTERNAL;                                            \
+    }                                                                          \
+    catch (...) {                                                              \
+        ::fbc::set_error(FBCORR_ERR_INTERNAL, "unknown exception");            \
+        return FBCORR_ERR_INTERNAL;                                            \
+    }
+
 // --------------------------------------------------------------- configs
 // A kernel configuration: ordered key -> integer map plus the algorithm.
 // Text form: "algo=igemm kc=8 s=1 ...".
 struct Config {
-    std::string algo;                 // "igemm", "direct", "dw"
+    std::string algo;                 // "igemm", "direct", "dw", "nn"
     std::map<std::string, int> v;
     int get(const char* k) const;
     std::string str() const;

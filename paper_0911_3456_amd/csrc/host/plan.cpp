@@ -177,17 +177,6 @@ using namespace fbc;
 
 // ====================================================================== C ABI
 
-#define FBC_API_BEGIN try {
-#define FBC_API_END                                                          \
-    }                                                                        \
-    catch (const std::exception& e) {                                        \
-        set_error(FBCORR_ERR_INTERNAL, std::string("exception: ") + e.what()); \
-        return FBCORR_ERR_INTERNAL;                                          \
-    }                                                                        \
-    catch (...) {                                                            \
-        set_error(FBCORR_ERR_INTERNAL, "unknown exception");                 \
-        return FBCORR_ERR_INTERNAL;                                          \
-    }
 
 extern "C" {
 

@@ -6,6 +6,7 @@
 // This is that database.  One entry per line:
 //
 //   <arch> <role> <precision> <batch> <H> <W> <D> <N> <fh> <fw> : <config text>
+//   <arch> nearest u8 <T> <M> <D> : <config text>      (nearest-neighbour search)
 //
 // '#' starts a comment.  The file is tuning_db.txt next to libfbcorr.so, or
 // the path in FBCORR_TUNING_DB.  fbcorr_tune can record its winner here.
@@ -72,26 +73,35 @@ static void load_locked() {
     }
 }
 
-bool tuning_db_lookup(const std::string& arch, int role, const fbcorr_desc& d, std::string& cfg) {
+bool tuning_db_lookup_key(const std::string& key, std::string& cfg) {
     std::lock_guard<std::mutex> lk(g_db_mu);
     load_locked();
-    auto it = g_db.find(db_key(arch, role, d));
+    auto it = g_db.find(key);
     if (it == g_db.end()) return false;
     cfg = it->second;
     return true;
 }
 
+bool tuning_db_lookup(const std::string& arch, int role, const fbcorr_desc& d, std::string& cfg) {
+    return tuning_db_lookup_key(db_key(arch, role, d), cfg);
+}
+
 bool tuning_db_record(const std::string& arch, int role, const fbcorr_desc& d, const std::string& cfg,
                       std::string& err) {
+    return tuning_db_record_key(db_key(arch, role, d), cfg, err);
+}
+
+bool tuning_db_record_key(const std::string& key, const std::string& cfg, std::string& err) {
     std::lock_guard<std::mutex> lk(g_db_mu);
     load_locked();
-    g_db[db_key(arch, role, d)] = cfg;
+    g_db[key] = cfg;
     const std::string path = tuning_db_path();
     const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
     {
         std::ofstream out(tmp);
         if (!out) { err = "cannot write " + tmp; return false; }
-        out << "# fbcorr tuning database: <arch> <role> <precision> <batch> <H> <W> <D> <N> <fh> <fw> : <config>\n";
+        out << "# fbcorr tuning database: <arch> <role> <precision> <batch> <H> <W> <D> <N> <fh> <fw> : <config>\n"
+               "#                          <arch> nearest u8 <T> <M> <D> : <config>\n";
         for (auto& kv : g_db) out << kv.first << " : " << kv.second << "\n";
     }
     if (rename(tmp.c_str(), path.c_str()) != 0) { err = "cannot replace " + path; return false; }

@@ -1,0 +1,188 @@
+"""GPU parity of the exact nearest-neighbour search (Sec. 6.4) against the
+CPU oracle, through the C ABI.
+
+Bar: bit-exact.  The search is integer arithmetic end to end, so idx (the
+lowest index at the smallest distance) and dist (the squared distance) must
+equal the oracle's exactly, on every target, for every configuration.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+from _gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+# Explicit configurations the tests install (validated on the host by
+# tests/test_abi_nn.py before any GPU run).
+NN_CFGS = ["nt=1 wv=1 ch=1 pf=0", "nt=2 wv=4 ch=3 pf=1", "nt=4 wv=4 ch=64 pf=1", "nt=8 wv=2 ch=1000 pf=1",
+           "nt=4 wv=8 ch=7 pf=0 xcd=0", "nt=1 wv=2 ch=2 fw=1", "nt=8 wv=1 ch=16 fw=16"]
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _search(t, n, cfg=None, plan=None):
+    from paper_0911_3456_amd import NNPlan
+    if plan is None:
+        plan = NNPlan(t.shape[0], n.shape[0], t.shape[1])
+    if cfg:
+        plan.set_config(cfg)
+    idx, dist = plan.search(_dev(t), _dev(n))
+    torch.cuda.synchronize()
+    return idx.cpu().numpy().astype(np.int64), dist.cpu().numpy().astype(np.int64), plan
+
+
+def _assert_exact(t, n, idx, dist, what):
+    ri, rd = oracle.nearest(t, n)
+    bad = np.flatnonzero((idx != ri) | (dist != rd))
+    assert bad.size == 0, "%s: %d mismatches, first target %d: gpu (%d, %d) oracle (%d, %d)" % (
+        what, bad.size, bad[0], idx[bad[0]], dist[bad[0]], ri[bad[0]], rd[bad[0]])
+
+
+SHAPES = [
+    # T, M, D -- ragged target blocks and neighbour tiles, partial K blocks
+    (300, 5000, 64), (17, 33, 64), (1, 1, 64), (5, 16, 16), (64, 1000, 128), (37, 777, 48),
+    (129, 4099, 64), (40, 300, 512), (1000, 20000, 64),
+]
+
+
+@pytest.mark.parametrize("T,M,D", SHAPES)
+def test_default_config_exact(T, M, D):
+    need_gpu()
+    rng = np.random.default_rng(T * 7 + M + D)
+    if D == 64:
+        t, n = wl.draw_nn(T, M, seed=T + M)
+    else:
+        t = rng.integers(0, 256, (T, D), dtype=np.uint8)
+        n = rng.integers(0, 256, (M, D), dtype=np.uint8)
+    idx, dist, plan = _search(t, n)
+    print((T, M, D), plan.get_config())
+    _assert_exact(t, n, idx, dist, str((T, M, D)))
+
+
+@pytest.mark.parametrize("cfg", NN_CFGS)
+def test_configurations_exact(cfg):
+    need_gpu()
+    for T, M, D in [(300, 5000, 64), (37, 777, 48)]:
+        rng = np.random.default_rng(5)
+        t = rng.integers(0, 256, (T, D), dtype=np.uint8)
+        n = rng.integers(0, 256, (M, D), dtype=np.uint8)
+        idx, dist, plan = _search(t, n, cfg)
+        print(cfg, "->", plan.get_config())
+        _assert_exact(t, n, idx, dist, cfg)
+
+
+@pytest.mark.parametrize("cfg", [None, "nt=1 wv=1 ch=1", "nt=4 wv=4 ch=5"])
+def test_ties_and_duplicates(cfg):
+    """Equal distances must resolve to the lowest index wherever the equal
+    rows fall: same tile, same row group, other chunks, other lane groups."""
+    need_gpu()
+    t, n = wl.draw_nn(200, 3000, seed=12)
+    n = n.copy()
+    # duplicates of earlier rows at many offsets (tile, group and chunk boundaries)
+    for k, (src, dst) in enumerate([(5, 6), (5, 7), (5, 2999), (16, 31), (16, 47), (100, 1601), (3, 80),
+                                    (1000, 1004), (1000, 1008), (2000, 2016), (40, 1)]):
+        n[dst] = n[src]
+    t = t.copy()
+    t[:20] = n[[5, 6, 7, 2999, 16, 31, 47, 100, 1601, 3, 80, 1000, 1004, 1008, 2000, 2016, 40, 1, 0, 2998]]
+    # near-ties: a neighbour at distance 1 in two places
+    t[20] = n[500]
+    t[20, 0] = n[500, 0] ^ 1
+    n[2500] = t[20]
+    n[2500, 1] = t[20, 1] ^ 1 if t[20, 1] < 255 else 254
+    idx, dist, _ = _search(t, n, cfg)
+    _assert_exact(t, n, idx, dist, "ties %s" % cfg)
+    assert dist[:20].tolist() == [0] * 20
+
+
+def test_identical_neighbours_and_extremes():
+    need_gpu()
+    # every neighbour identical: index 0 for every target
+    n = np.full((4100, 64), 77, np.uint8)
+    t = np.random.default_rng(1).integers(0, 256, (70, 64), dtype=np.uint8)
+    idx, dist, _ = _search(t, n)
+    assert (idx == 0).all()
+    _assert_exact(t, n, idx, dist, "identical")
+    # the extremes of the integer range: 0 against 255 everywhere
+    n = np.concatenate([np.zeros((3, 64), np.uint8), np.full((5, 64), 255, np.uint8)])
+    t = np.concatenate([np.zeros((2, 64), np.uint8), np.full((2, 64), 255, np.uint8),
+                        np.full((1, 64), 127, np.uint8), np.full((1, 64), 128, np.uint8)])
+    idx, dist, _ = _search(t, n)
+    _assert_exact(t, n, idx, dist, "extremes")
+    assert idx.tolist() == [0, 0, 3, 3, 0, 3]
+    assert dist.tolist() == [0, 0, 0, 0, 64 * 127 ** 2, 64 * 127 ** 2]
+    # a 512-byte patch at the far end of the range
+    n = np.full((20, 512), 255, np.uint8)
+    n[7] = 0
+    t = np.zeros((3, 512), np.uint8)
+    idx, dist, _ = _search(t, n)
+    assert idx.tolist() == [7, 7, 7] and dist.tolist() == [0, 0, 0]
+    t = np.full((3, 512), 255, np.uint8)
+    t[1] = 0
+    n = np.zeros((20, 512), np.uint8)
+    idx, dist, _ = _search(t, n)
+    assert dist.tolist() == [512 * 255 ** 2, 0, 512 * 255 ** 2] and idx.tolist() == [0, 0, 0]
+
+
+def test_no_targets():
+    need_gpu()
+    from paper_0911_3456_amd import NNPlan
+    plan = NNPlan(0, 100, 64)
+    n = _dev(np.zeros((100, 64), np.uint8))
+    idx, dist = plan.search(_dev(np.zeros((0, 64), np.uint8)), n)
+    assert idx.numel() == 0 and dist.numel() == 0
+
+
+def test_paper_size_sampled():
+    """4096 targets against 1,048,576 neighbours (the largest row of the
+    paper's table), in the configuration the benchmark runs: a sample of
+    targets against the oracle, and every target's distance recomputed from
+    the row it names."""
+    need_gpu()
+    T, M = wl.NN_TARGETS, wl.NN_NEIGHBOURS[-1]
+    t, n = wl.draw_nn(T, M, seed=7)
+    idx, dist, plan = _search(t, n)
+    print(plan.get_config())
+    sample = np.random.default_rng(0).choice(T, 48, replace=False)
+    sample = np.concatenate([[0, T - 1], sample])
+    ri, rd = oracle.nearest(t[sample], n)
+    np.testing.assert_array_equal(idx[sample], ri)
+    np.testing.assert_array_equal(dist[sample], rd)
+    assert (idx >= 0).all() and (idx < M).all()
+    recomputed = ((t.astype(np.int64) - n[idx].astype(np.int64)) ** 2).sum(1)
+    np.testing.assert_array_equal(recomputed, dist)
+
+
+def test_tuning_keeps_exactness():
+    need_gpu()
+    t, n = wl.draw_nn(512, 20000, seed=13)
+    from paper_0911_3456_amd import NNPlan
+    plan = NNPlan(512, 20000, 64)
+    rep = plan.tune(_dev(t), _dev(n), warmup=1, reps=3, max_candidates=12)
+    print(rep)
+    assert rep["n_compiled"] >= 1 and rep["n_rejected_parity"] == 0
+    assert rep["best_ms"] <= rep["default_ms"]
+    idx, dist, _ = _search(t, n, plan=plan)
+    _assert_exact(t, n, idx, dist, "tuned " + plan.get_config())
+
+
+def test_timing_and_config_roundtrip():
+    need_gpu()
+    from paper_0911_3456_amd import FbcorrError, NNPlan
+    t, n = wl.draw_nn(64, 4096, seed=14)
+    plan = NNPlan(64, 4096, 64)
+    plan.enable_timing(True)
+    for _ in range(3):
+        _search(t, n, plan=plan)
+    tm = plan.read_timing()
+    assert all(tm[k][1] == 3 and tm[k][0] > 0 for k in ("norms", "scan", "final"))
+    before = plan.get_config()
+    with pytest.raises(FbcorrError):
+        plan.set_config("nt=99")
+    assert plan.get_config() == before
+    plan.set_config("nt=2 ch=4")
+    assert "nt=2" in plan.get_config() and "ch=4" in plan.get_config()
