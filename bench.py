@@ -466,6 +466,19 @@ def main():
                    "kernels": {r: plan.get_config(r) for r in ROLES}},
         "roofline": roofline,
     }
+    if args.only == "step":
+        # the same step with dW overlapped on a side stream (FBCORR_FLAG_OVERLAP_BACKWARD)
+        po = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, device=dev, overlap_backward=True)
+        for r in ROLES:
+            po.set_config(r, plan.get_config(r).split(" (")[0])
+
+        def step_overlapped():
+            po.forward(xt, wt, y)
+            po.backward(xt, wt, gt, dx=dx, dw=dw)
+        so = time_steps(step_overlapped, args.steps, args.warmup)
+        result["overlapped_backward"] = {"ms_per_step": round(so * 1e3, 5),
+                                         "gflops": round(flops_step / so / 1e9, 3)}
+        po.close()
     if tune_reports:
         result["tune"] = tune_reports
     if not args.no_precision and args.only == "step":

@@ -96,8 +96,14 @@ typedef struct fbcorr_desc {
     int32_t batch, H, W, D, N, fh, fw;
     int32_t precision; /* fbcorr_precision */
     int32_t algo;      /* fbcorr_algo */
-    uint32_t flags;    /* reserved, must be 0 */
+    uint32_t flags;    /* FBCORR_FLAG_* bits; others must be 0 */
 } fbcorr_desc;
+
+/* fbcorr_backward with both gradients runs dW on a plan-owned side stream
+ * (default priority), forked from and joined back into the caller's stream,
+ * concurrently with dX.  Off by default: the kernels then run one after the
+ * other on the caller's stream, so each one's time is its own. */
+#define FBCORR_FLAG_OVERLAP_BACKWARD 1u
 
 typedef struct fbcorr_plan_s* fbcorr_plan_t;
 

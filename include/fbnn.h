@@ -50,10 +50,12 @@ typedef struct fbnn_desc {
 typedef struct fbnn_plan_s* fbnn_plan_t;
 
 /* Create a plan on HIP device `device`: validates the descriptor, picks the
- * configuration (tuning database, else a heuristic) and compiles the three
- * kernels (row norms, scan, final selection).  FBCORR_ERR_SHAPE for a bad
- * descriptor, FBCORR_ERR_NO_DEVICE, FBCORR_ERR_UNSUPPORTED for a device that
- * is not gfx950, FBCORR_ERR_COMPILE with the hiprtc log. */
+ * configuration (tuning database, else a heuristic) and compiles the five
+ * kernels (neighbour norms, prefix sums, parity partition, scan, final
+ * selection).  FBCORR_ERR_INVALID_ARGUMENT for a bad descriptor,
+ * FBCORR_ERR_NO_DEVICE, FBCORR_ERR_UNSUPPORTED for a device that is not
+ * gfx950 or more rows than the index type holds, FBCORR_ERR_COMPILE with the
+ * hiprtc log. */
 FBCORR_API fbcorr_status fbnn_plan(const fbnn_desc* desc, int device, fbnn_plan_t* out);
 FBCORR_API fbcorr_status fbnn_plan_destroy(fbnn_plan_t plan);
 
@@ -63,7 +65,7 @@ FBCORR_API fbcorr_status fbnn_workspace_size(fbnn_plan_t plan, int pass, size_t*
 
 /* Nearest neighbour of every target.  targets [T][D] and neighbors [M][D]
  * (uint8), idx [T] and dist [T] (int32), workspace of fbnn_workspace_size(0)
- * bytes; all device pointers, 16-byte aligned.  Enqueues three kernels on
+ * bytes; all device pointers, 16-byte aligned.  Enqueues five kernels on
  * `stream`.  FBCORR_ERR_INVALID_ARGUMENT for NULL or misaligned pointers,
  * FBCORR_ERR_WORKSPACE for a short workspace, FBCORR_ERR_LAUNCH if HIP
  * refuses a launch (the plan is then not guaranteed usable). */
@@ -73,9 +75,10 @@ FBCORR_API fbcorr_status fbnn_search(fbnn_plan_t plan, const uint8_t* targets, c
 
 /* Auto-tuning (Sec. 4.1 and 6.2 applied to this search): enumerates
  * configurations (targets per wave, waves per workgroup, neighbour chunk
- * length, load-ahead), compiles them in parallel, requires each to return
- * the default's idx and dist bit for bit on the caller's data, times the
- * survivors with HIP events (median of opts->reps) and installs the fastest.
+ * length, tiles per tracking group, load-ahead), compiles them in
+ * parallel, requires each to return the default's idx and dist bit for bit
+ * on the caller's data, times the survivors with HIP events (median of
+ * opts->reps) and installs the fastest.
  * opts->role is ignored; opts->flags bit 1 records the winner in the tuning
  * database.  Synchronises `stream`. */
 FBCORR_API fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t* neighbors,
@@ -88,12 +91,13 @@ FBCORR_API fbcorr_status fbnn_plan_get_config(fbnn_plan_t plan, char* buf, size_
 FBCORR_API fbcorr_status fbnn_plan_set_config(fbnn_plan_t plan, const char* cfg);
 
 /* Kernel timing with HIP events on the caller's stream: ms[0..2] = total
- * milliseconds of the norm, scan and final kernels, calls[0..2] = launches;
- * read_timing synchronises the recorded events. */
+ * milliseconds of the neighbour preparation (norms, prefix sums, parity
+ * partition: three kernels), the scan kernel and the final selection;
+ * calls[0..2] = searches timed.  read_timing synchronises the events. */
 FBCORR_API fbcorr_status fbnn_plan_enable_timing(fbnn_plan_t plan, int enable);
 FBCORR_API fbcorr_status fbnn_plan_read_timing(fbnn_plan_t plan, double* ms, int64_t* calls, int reset);
 
-/* Generate and compile (hiprtc, no device needed) the three kernels of a
+/* Generate and compile (hiprtc, no device needed) the five kernels of a
  * descriptor and configuration for `arch` (NULL = "gfx950"); reports the
  * total code-object size.  Host-only. */
 FBCORR_API fbcorr_status fbnn_compile_check(const fbnn_desc* desc, const char* cfg, const char* arch,

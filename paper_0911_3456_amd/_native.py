@@ -148,8 +148,11 @@ def check(status: int) -> None:
         raise FbcorrError(status, msg or STATUS_NAMES.get(status, str(status)))
 
 
-def make_desc(batch, H, W, D, N, fh, fw, precision="fp32", algo="auto") -> Desc:
-    return Desc(batch, H, W, D, N, fh, fw, PRECISIONS[precision], ALGOS[algo], 0)
+FLAG_OVERLAP_BACKWARD = 1
+
+
+def make_desc(batch, H, W, D, N, fh, fw, precision="fp32", algo="auto", flags=0) -> Desc:
+    return Desc(batch, H, W, D, N, fh, fw, PRECISIONS[precision], ALGOS[algo], flags)
 
 
 def codegen(desc: Desc, role: str = "forward", cfg: str | None = None):

@@ -1,11 +1,12 @@
 // Exact nearest-neighbour search (Sec. 6.4) behind the fbnn_* entry points:
 // plans, run-time specialised kernels, launches, timing and tuning.
 //
-// A search is three kernels from nn.hip: the neighbour norms (-|n|^2 per
-// row, with a sentinel for the padding rows of the last tile), the int8
-// matrix-core scan that keeps, per target and neighbour chunk, the best
-// score and the first row group reaching it, and the final selection that
-// merges the chunks and recomputes four exact distances per target.
+// A search is five kernels from nn.hip: the neighbour norms with per-block
+// counts of even norms, their prefix sums, the stable partition of the
+// neighbours by norm parity (index and half-norm score term per position),
+// the int8 matrix-core scan that keeps, per target and chunk, the best exact
+// score and the first tile group reaching it, and the final selection that
+// merges the chunks and re-measures that group's rows exactly.
 #include "plan.h"
 #include "fbnn.h"
 
@@ -22,16 +23,19 @@ namespace {
 constexpr int kScoreTargets = 2048;   // workgroups the default chunking aims for
 
 struct NNGeom {
-    int nt = 0, wv = 0, ch = 0, fw = 0;
-    long tpg = 0, tb = 0, mt = 0, nchk = 0;
-    LaunchGeom norms, scan, fin;
-    size_t off_cneg = 0, off_part = 0, ws_bytes = 0;
+    int nt = 0, wv = 0, ch = 0, fw = 0, tg = 0;
+    long tpg = 0, tb = 0, mt1 = 0, nblk = 0, nchk = 0;
+    LaunchGeom norms, offsets, scatter, scan, fin;
+    size_t off_hdr = 0, off_nn = 0, off_cnt = 0, off_perm = 0, off_cneg = 0, off_part = 0, ws_bytes = 0;
 };
+
+// The five kernels of a search, in launch order.
+enum { K_NORMS, K_OFFSETS, K_SCATTER, K_SCAN, K_FINAL, K_COUNT };
 
 struct NNBuild {
     Config cfg;
     NNGeom g;
-    KernelSource norms, scan, fin;
+    KernelSource ks[K_COUNT];
 };
 
 struct NNPlan {
@@ -39,7 +43,7 @@ struct NNPlan {
     int device = 0;
     DeviceInfo dev;
     NNBuild build;
-    Kernel norms, scan, fin;
+    Kernel k[K_COUNT];
     std::mutex mu;
     bool timing = false;
     std::vector<std::array<hipEvent_t, 4>> pending;
@@ -78,14 +82,15 @@ int chunk_for(const fbnn_desc& d, int nt, int wv, long wgs) {
 Config heuristic(const fbnn_desc& d) {
     Config c;
     const int kb = (d.dim + 63) / 64;
-    const int nt = std::max(1, std::min(4, 16 / kb));   // target fragments stay <= 64 VGPRs
+    const int nt = std::max(1, std::min(8, 16 / kb));   // target fragments stay <= 64 VGPRs
     c.algo = "nn";
     c.v["nt"] = nt;
-    c.v["wv"] = 4;
+    c.v["wv"] = 8;
     c.v["pf"] = 1;
+    c.v["tg"] = 1;
     c.v["xcd"] = 1;
     c.v["fw"] = 4;
-    c.v["ch"] = chunk_for(d, nt, 4, kScoreTargets);
+    c.v["ch"] = chunk_for(d, nt, 8, kScoreTargets);
     return c;
 }
 
@@ -104,7 +109,7 @@ void opt(std::vector<std::string>& o, const char* k, long v) {
 }
 
 bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBuild& b, std::string& err) {
-    static const std::set<std::string> known = {"nt", "wv", "ch", "pf", "xcd", "fw", "inject_error"};
+    static const std::set<std::string> known = {"nt", "wv", "ch", "pf", "tg", "xcd", "fw", "inject_error"};
     if (c.algo != "nn") { err = "algo must be nn"; return false; }
     for (auto& kv : c.v)
         if (!known.count(kv.first)) { err = "unknown key '" + kv.first + "' for algo=nn"; return false; }
@@ -113,6 +118,7 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     g.wv = c.get("wv");
     g.ch = c.get("ch");
     g.fw = c.get("fw");
+    g.tg = c.get("tg");
     const int pf = c.get("pf"), xcd = c.get("xcd");
     const int kb = (d.dim + 63) / 64;
     if (g.nt < 1 || g.nt > 8) { err = "nt must be in [1, 8]"; return false; }
@@ -120,20 +126,29 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     if (g.wv < 1 || g.wv * 64 > di.max_threads) { err = "wv out of range"; return false; }
     if (g.fw < 1 || g.fw > 16) { err = "fw must be in [1, 16]"; return false; }
     if (g.ch < 1) { err = "ch must be >= 1"; return false; }
+    if (g.tg != 1 && g.tg != 2 && g.tg != 4) { err = "tg must be 1, 2 or 4"; return false; }
     if (pf < 0 || pf > 1 || xcd < 0 || xcd > 1) { err = "pf and xcd are 0 or 1"; return false; }
     const long T = d.n_targets;
     g.tpg = (long)g.wv * g.nt * 16;
     g.tb = std::max(1L, cdiv(T, g.tpg));
-    g.mt = cdiv(d.n_neighbors, 16);
-    g.ch = (int)std::min<long>(g.ch, g.mt);
-    g.nchk = cdiv(g.mt, g.ch);
+    g.mt1 = cdiv(d.n_neighbors, 16) + 1;       // both parity classes padded to whole tiles
+    g.nblk = cdiv(d.n_neighbors, 64);
+    g.ch = (int)std::min<long>(g.ch, g.mt1);
+    g.nchk = cdiv(g.mt1, g.ch);
     if (g.tb * g.nchk >= (1L << 31)) { err = "too many scan workgroups"; return false; }
-    g.norms = LaunchGeom{(int)cdiv(g.mt * 16 * 4, 256), 1, 256, 0};
+    g.norms = LaunchGeom{(int)g.nblk, 1, 256, 0};
+    g.offsets = LaunchGeom{1, 1, 1024, 0};
+    g.scatter = LaunchGeom{(int)g.nblk, 1, 64, 0};
     g.scan = LaunchGeom{(int)(g.tb * g.nchk), 1, g.wv * 64, 0};
     g.fin = LaunchGeom{(int)std::max(1L, cdiv(T, 64)), 1, g.fw * 64, 0};
-    g.off_cneg = 0;
-    g.off_part = align256((size_t)g.mt * 16 * 4);
-    g.ws_bytes = g.off_part + align256((size_t)g.nchk * (size_t)std::max(T, 1L) * 8);
+    size_t off = 0;
+    g.off_hdr = off;  off += 256;
+    g.off_nn = off;   off += align256((size_t)d.n_neighbors * 4);
+    g.off_cnt = off;  off += align256((size_t)g.nblk * 4);
+    g.off_perm = off; off += align256((size_t)g.mt1 * 16 * 4);
+    g.off_cneg = off; off += align256((size_t)g.mt1 * 16 * 4);
+    g.off_part = off; off += align256((size_t)g.nchk * (size_t)std::max(T, 1L) * 8);
+    g.ws_bytes = off;
     b.cfg = c;
     b.cfg.v["ch"] = g.ch;
 
@@ -148,68 +163,82 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
         opt(ks.options, "D", d.dim);
         if (c.get("inject_error")) ks.options.push_back("-DFB_INJECT_ERROR");
     };
-    base(b.norms, "fbnn_norms", "NN_NORMS");
-    base(b.scan, "fbnn_scan", "NN_SCAN");
-    opt(b.scan.options, "NT", g.nt);
-    opt(b.scan.options, "WV", g.wv);
-    opt(b.scan.options, "CH", g.ch);
-    opt(b.scan.options, "PF", pf);
-    opt(b.scan.options, "XCDMAP", xcd);
-    base(b.fin, "fbnn_final", "NN_FINAL");
-    opt(b.fin.options, "FW", g.fw);
-    opt(b.fin.options, "NCHK", g.nchk);
+    base(b.ks[K_NORMS], "fbnn_norms", "NN_NORMS");
+    base(b.ks[K_OFFSETS], "fbnn_offsets", "NN_OFFSETS");
+    base(b.ks[K_SCATTER], "fbnn_scatter", "NN_SCATTER");
+    base(b.ks[K_SCAN], "fbnn_scan", "NN_SCAN");
+    auto& sc = b.ks[K_SCAN].options;
+    opt(sc, "NT", g.nt);
+    opt(sc, "WV", g.wv);
+    opt(sc, "CH", g.ch);
+    opt(sc, "TG", g.tg);
+    opt(sc, "PF", pf);
+    opt(sc, "XCDMAP", xcd);
+    base(b.ks[K_FINAL], "fbnn_final", "NN_FINAL");
+    opt(b.ks[K_FINAL].options, "FW", g.fw);
+    opt(b.ks[K_FINAL].options, "TG", g.tg);
+    opt(b.ks[K_FINAL].options, "NCHK", g.nchk);
     return true;
 }
 
-fbcorr_status load_build(NNPlan* p, const NNBuild& b, Kernel& kn, Kernel& ks, Kernel& kf) {
-    fbcorr_status st = load_kernel(b.norms, p->device, kn);
-    if (st == FBCORR_OK) st = load_kernel(b.scan, p->device, ks);
-    if (st == FBCORR_OK) st = load_kernel(b.fin, p->device, kf);
-    return st;
+fbcorr_status load_build(NNPlan* p, const NNBuild& b, Kernel* k) {
+    for (int i = 0; i < K_COUNT; ++i) {
+        fbcorr_status st = load_kernel(b.ks[i], p->device, k[i]);
+        if (st != FBCORR_OK) return st;
+    }
+    return FBCORR_OK;
 }
 
 fbcorr_status install(NNPlan* p, const Config& c) {
     NNBuild b;
     std::string err;
     FBC_RETURN_IF(!make_build(p->desc, c, p->dev, b, err), FBCORR_ERR_UNSUPPORTED, err);
-    Kernel kn, ks, kf;
-    fbcorr_status st = load_build(p, b, kn, ks, kf);
+    Kernel k[K_COUNT];
+    fbcorr_status st = load_build(p, b, k);
     if (st != FBCORR_OK) return st;
     std::lock_guard<std::mutex> lk(p->mu);
     p->build = b;
-    p->norms = kn;
-    p->scan = ks;
-    p->fin = kf;
+    for (int i = 0; i < K_COUNT; ++i) p->k[i] = k[i];
     return FBCORR_OK;
 }
 
-// Enqueue the three kernels of one search.
-fbcorr_status run(const NNPlan* p, const NNBuild& b, const Kernel& kn, const Kernel& ks, const Kernel& kf,
-                  const uint8_t* tg, const uint8_t* nb, int32_t* idx, int32_t* dist, void* ws, hipStream_t s,
-                  hipEvent_t* ev) {
+// Enqueue the five kernels of one search.  With events: ev[0] before the
+// neighbour preparation, ev[1] before the scan, ev[2] before the final
+// selection, ev[3] after it.
+fbcorr_status run(const NNBuild& b, const Kernel* k, const uint8_t* tg, const uint8_t* nb, int32_t* idx,
+                  int32_t* dist, void* ws, hipStream_t s, hipEvent_t* ev) {
     char* base = (char*)ws;
+    int* hdr = (int*)(base + b.g.off_hdr);
+    int* nn = (int*)(base + b.g.off_nn);
+    int* cnt = (int*)(base + b.g.off_cnt);
+    int* perm = (int*)(base + b.g.off_perm);
     int* cneg = (int*)(base + b.g.off_cneg);
     unsigned long long* part = (unsigned long long*)(base + b.g.off_part);
+    fbcorr_status st;
     if (ev) hipEventRecord(ev[0], s);
     {
-        void* args[] = {&nb, &cneg};
-        fbcorr_status st = launch(kn, b.g.norms, s, args);
-        if (st != FBCORR_OK) return st;
+        void* args[] = {&nb, &nn, &cnt};
+        if ((st = launch(k[K_NORMS], b.g.norms, s, args))) return st;
+    }
+    {
+        void* args[] = {&cnt, &hdr, &perm, &cneg};
+        if ((st = launch(k[K_OFFSETS], b.g.offsets, s, args))) return st;
+    }
+    {
+        void* args[] = {&nn, &cnt, &hdr, &perm, &cneg};
+        if ((st = launch(k[K_SCATTER], b.g.scatter, s, args))) return st;
     }
     if (ev) hipEventRecord(ev[1], s);
     {
-        void* args[] = {&tg, &nb, &cneg, &part};
-        fbcorr_status st = launch(ks, b.g.scan, s, args);
-        if (st != FBCORR_OK) return st;
+        void* args[] = {&tg, &nb, &perm, &cneg, &hdr, &part};
+        if ((st = launch(k[K_SCAN], b.g.scan, s, args))) return st;
     }
     if (ev) hipEventRecord(ev[2], s);
     {
-        void* args[] = {&tg, &nb, &part, &idx, &dist};
-        fbcorr_status st = launch(kf, b.g.fin, s, args);
-        if (st != FBCORR_OK) return st;
+        void* args[] = {&tg, &nb, &perm, &part, &idx, &dist};
+        if ((st = launch(k[K_FINAL], b.g.fin, s, args))) return st;
     }
     if (ev) hipEventRecord(ev[3], s);
-    (void)p;
     return FBCORR_OK;
 }
 
@@ -229,21 +258,23 @@ std::vector<Config> candidates(const fbnn_desc& d) {
     std::vector<Config> out;
     std::set<std::string> seen;
     const int kb = (d.dim + 63) / 64;
-    for (int nt : {1, 2, 4, 8})
-        for (int wv : {1, 2, 4, 8})
-            for (long wgs : {256L, 512L, 1024L, 2048L, 4096L, 8192L})
-                for (int pf : {0, 1}) {
-                    if (nt * kb > 16) continue;
-                    Config c;
-                    c.algo = "nn";
-                    c.v["nt"] = nt;
-                    c.v["wv"] = wv;
-                    c.v["pf"] = pf;
-                    c.v["xcd"] = 1;
-                    c.v["fw"] = 4;
-                    c.v["ch"] = chunk_for(d, nt, wv, wgs);
-                    if (seen.insert(c.str()).second) out.push_back(c);
-                }
+    for (int nt : {2, 4, 8})
+        for (int wv : {2, 4, 8})
+            for (long wgs : {512L, 1024L, 2048L, 4096L})
+                for (int pf : {0, 1})
+                    for (int tg : {1, 2}) {
+                        if (nt * kb > 16) continue;
+                        Config c;
+                        c.algo = "nn";
+                        c.v["nt"] = nt;
+                        c.v["wv"] = wv;
+                        c.v["pf"] = pf;
+                        c.v["tg"] = tg;
+                        c.v["xcd"] = 1;
+                        c.v["fw"] = 4;
+                        c.v["ch"] = chunk_for(d, nt, wv, wgs);
+                        if (seen.insert(c.str()).second) out.push_back(c);
+                    }
     return out;
 }
 
@@ -327,14 +358,12 @@ fbcorr_status fbnn_search(fbnn_plan_t plan, const uint8_t* targets, const uint8_
         (st = check_ptr(idx, "idx")) || (st = check_ptr(dist, "dist")))
         return st;
     NNBuild b;
-    Kernel kn, ks, kf;
+    Kernel k[K_COUNT];
     bool timing;
     {
         std::lock_guard<std::mutex> lk(p->mu);
         b = p->build;
-        kn = p->norms;
-        ks = p->scan;
-        kf = p->fin;
+        for (int i = 0; i < K_COUNT; ++i) k[i] = p->k[i];
         timing = p->timing;
     }
     if ((st = check_ws(workspace, workspace_bytes, b.g.ws_bytes))) return st;
@@ -343,7 +372,7 @@ fbcorr_status fbnn_search(fbnn_plan_t plan, const uint8_t* targets, const uint8_
     std::array<hipEvent_t, 4> ev{};
     if (timing)
         for (auto& e : ev) hipEventCreate(&e);
-    st = run(p, b, kn, ks, kf, targets, neighbors, idx, dist, workspace, s, timing ? ev.data() : nullptr);
+    st = run(b, k, targets, neighbors, idx, dist, workspace, s, timing ? ev.data() : nullptr);
     if (timing) {
         std::lock_guard<std::mutex> lk(p->mu);
         p->pending.push_back(ev);
@@ -439,9 +468,9 @@ fbcorr_status fbnn_compile_check(const fbnn_desc* desc, const char* cfg, const c
     NNBuild b;
     FBC_RETURN_IF(!make_build(*desc, c, di, b, err), FBCORR_ERR_UNSUPPORTED, err);
     size_t total = 0;
-    for (const KernelSource* ks : {&b.norms, &b.scan, &b.fin}) {
+    for (const KernelSource& ks : b.ks) {
         std::shared_ptr<const std::vector<char>> code;
-        st = compile_cached(*ks, di.arch, code);
+        st = compile_cached(ks, di.arch, code);
         if (st != FBCORR_OK) return st;
         total += code->size();
     }
@@ -481,16 +510,16 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
     fbcorr_tune_report rep;
     memset(&rep, 0, sizeof rep);
 
-    auto time_it = [&](const NNBuild& b, const Kernel& kn, const Kernel& ks, const Kernel& kf, int32_t* oi,
+    auto time_it = [&](const NNBuild& b, const Kernel* k, int32_t* oi,
                        int32_t* od, double& ms) -> fbcorr_status {
         fbcorr_status r = FBCORR_OK;
         for (int i = 0; i < warmup && r == FBCORR_OK; ++i)
-            r = run(p, b, kn, ks, kf, targets, neighbors, oi, od, workspace, s, nullptr);
+            r = run(b, k, targets, neighbors, oi, od, workspace, s, nullptr);
         std::vector<hipEvent_t> ev(reps + 1);
         for (auto& e : ev) hipEventCreate(&e);
         hipEventRecord(ev[0], s);
         for (int i = 0; i < reps && r == FBCORR_OK; ++i) {
-            r = run(p, b, kn, ks, kf, targets, neighbors, oi, od, workspace, s, nullptr);
+            r = run(b, k, targets, neighbors, oi, od, workspace, s, nullptr);
             hipEventRecord(ev[i + 1], s);
         }
         hipError_t he = hipStreamSynchronize(s);
@@ -513,10 +542,10 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
     std::string err;
     const Config dcfg = heuristic(p->desc);
     FBC_RETURN_IF(!make_build(p->desc, dcfg, p->dev, db, err), FBCORR_ERR_INTERNAL, "default: " + err);
-    Kernel dn, ds, dfin;
-    if ((st = load_build(p, db, dn, ds, dfin))) return st;
+    Kernel dk[K_COUNT];
+    if ((st = load_build(p, db, dk))) return st;
     double dms = 0;
-    if ((st = time_it(db, dn, ds, dfin, ref_i, ref_d, dms))) return st;
+    if ((st = time_it(db, dk, ref_i, ref_d, dms))) return st;
     std::vector<int32_t> hi(T), hd(T), ci(T), cd(T);
     hipError_t he = hipMemcpyDtoH(hi.data(), (hipDeviceptr_t)ref_i, T * 4);
     if (he == hipSuccess) he = hipMemcpyDtoH(hd.data(), (hipDeviceptr_t)ref_d, T * 4);
@@ -548,8 +577,8 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
         auto worker = [&]() {
             for (size_t i; (i = next.fetch_add(1)) < builds.size();) {
                 std::shared_ptr<const std::vector<char>> code;
-                for (const KernelSource* ks : {&builds[i].norms, &builds[i].scan, &builds[i].fin}) {
-                    res[i] = compile_cached(*ks, p->dev.arch, code);
+                for (const KernelSource& ks : builds[i].ks) {
+                    res[i] = compile_cached(ks, p->dev.arch, code);
                     if (res[i] != FBCORR_OK) break;
                 }
             }
@@ -570,15 +599,15 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
     double best = dms;
     NNBuild win = db;
     for (auto& b : builds) {
-        Kernel kn, ks, kf;
-        if (load_build(p, b, kn, ks, kf) != FBCORR_OK) {
+        Kernel k[K_COUNT];
+        if (load_build(p, b, k) != FBCORR_OK) {
             ++rep.n_failed;
             clear_error();
             continue;
         }
         ++rep.n_compiled;
         double ms = 0;
-        if ((st = time_it(b, kn, ks, kf, cand_i, cand_d, ms))) return st;
+        if ((st = time_it(b, k, cand_i, cand_d, ms))) return st;
         he = hipMemcpyDtoH(ci.data(), (hipDeviceptr_t)cand_i, T * 4);
         if (he == hipSuccess) he = hipMemcpyDtoH(cd.data(), (hipDeviceptr_t)cand_d, T * 4);
         FBC_RETURN_IF(he != hipSuccess, FBCORR_ERR_LAUNCH, std::string("copy: ") + hipGetErrorString(he));

@@ -27,7 +27,8 @@ fbcorr_status validate_desc(const fbcorr_desc* d) {
                   "unknown algorithm");
     FBC_RETURN_IF(d->algo == FBCORR_ALGO_DIRECT && d->precision != FBCORR_FP32, FBCORR_ERR_UNSUPPORTED,
                   "the direct kernel computes in fp32 only");
-    FBC_RETURN_IF(d->flags != 0, FBCORR_ERR_INVALID_ARGUMENT, "flags must be 0");
+    FBC_RETURN_IF((d->flags & ~FBCORR_FLAG_OVERLAP_BACKWARD) != 0, FBCORR_ERR_INVALID_ARGUMENT,
+                  "unknown bits in flags");
     const double elems_x = (double)d->batch * d->H * d->W * d->D;
     const double elems_y = (double)d->batch * (d->H - d->fh + 1) * (d->W - d->fw + 1) * d->N;
     FBC_RETURN_IF(elems_x > 2.0e9 || elems_y > 2.0e9, FBCORR_ERR_UNSUPPORTED, "tensor larger than 2^31 elements");
@@ -302,12 +303,12 @@ fbcorr_status fbcorr_backward(fbcorr_plan_t plan, const float* x, const float* w
     const size_t need = backward_ws(p, &off_w);
     if ((st = check_ws(workspace, workspace_bytes, need))) return st;
     hipStream_t s = (hipStream_t)stream;
-    if (dx && dw) {
+    if (dx && dw && (p->desc.flags & FBCORR_FLAG_OVERLAP_BACKWARD)) {
         // The two gradients are independent: dW goes to a side stream forked
-        // from the caller's stream and joined back, so the tail of one
-        // kernel overlaps the other.  (Default-priority stream; the event
-        // pair also works under graph capture.)  Calls from several threads
-        // enqueue their fork/join sequences one at a time.
+        // from the caller's stream and joined back, so the two kernels
+        // overlap.  (Default-priority stream; the event pair also works under
+        // graph capture.)  Calls from several threads enqueue their
+        // fork/join sequences one at a time.
         std::lock_guard<std::mutex> side_lock(p->side_mu);
         if (!p->side) {
             hipError_t e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);

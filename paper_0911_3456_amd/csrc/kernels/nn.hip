@@ -6,36 +6,54 @@
 //   idx[t]  = lowest m attaining it.
 //
 // Pixels are centred, c = p - 128 (a byte XOR 0x80 read as a signed byte),
-// which leaves every difference unchanged.  With |t|^2 fixed per target,
-// the nearest neighbour maximises the integer score
+// which leaves every difference unchanged.  With |t|^2 fixed per target the
+// nearest neighbour maximises the exact integer score
 //
-//   s(t, m) = 2 t.n_m - |n_m|^2        (= |t|^2 - dist(t, m)).
+//   S(t, m) = 2 t.n_m - |n_m|^2          (= |t|^2 - dist(t, m)).
 //
-// fbnn_norms    cneg[m] = -|n_m|^2 for m < M; a sentinel far below every
-//               real score for the padding rows of the last 16-row tile.
-// fbnn_scan     one workgroup = a block of targets x a chunk of CH neighbour
-//               tiles (16 rows each).  A v_mfma_i32_16x16x64_i8 product of a
-//               neighbour tile (rows) with 16 targets (columns) starts from
-//               the -|n|^2 rows and runs twice over the same operands, which
-//               gives s exactly in int32 (no rounding anywhere).  Lane l
-//               holds target l%16 against rows 4(l/16)..+3 of the tile, so
-//               it keeps one running maximum and the first tile at which it
-//               was reached; a later tile only replaces it when strictly
-//               greater.  The four lane groups of a target are merged on the
-//               key (score, then the lower first-row index), and the
-//               chunk's key is written to part[chunk][t].
-// fbnn_final    per target: the maximum key over all chunks names a group of
-//               four consecutive rows that holds the lowest-index nearest
-//               neighbour (tiles are visited in increasing order inside a
-//               chunk, chunks and groups cover disjoint increasing ranges);
-//               the four exact distances are recomputed from the bytes.
+// 2t does not fit in int8, so the matrix cores compute the half score
+// s(t, m) = t.n_m - floor(|n_m|^2 / 2) in one pass, and S = 2s - (|n_m|^2
+// odd).  Inside a set of neighbours whose |n|^2 have the same parity, s
+// orders them exactly as S does; two neighbours of different parity never
+// have equal S.  The neighbours are therefore partitioned, stably, into an
+// even class and an odd class, each padded to whole 16-row tiles, and the
+// scan runs on the partitioned order:
+//
+// fbnn_norms    |n_m|^2 for every row (4 lanes per row) and the number of
+//               even rows of each 64-row block.
+// fbnn_offsets  one workgroup: exclusive prefix sum of the block counts
+//               (in place), the class sizes, and the padding entries
+//               (index -1, score term far below any real score).
+// fbnn_scatter  perm[pos] = m and cneg[pos] = -floor(|n_m|^2 / 2), with pos
+//               the row's place in its class (stable: lane order inside a
+//               block, blocks in order); the odd class starts at the first
+//               tile after the even class.
+// fbnn_scan     one workgroup = a block of targets x a chunk of CH tiles of
+//               the partitioned order.  A v_mfma_i32_16x16x64_i8 product of a
+//               tile (rows = neighbours, gathered through perm) with 16
+//               targets (columns), started from the rows' cneg values, gives
+//               s exactly in int32.  Lane l holds target l%16 against rows
+//               4(l/16)..+3 of the tile and keeps a running maximum over
+//               groups of TG tiles and the first group reaching it (later
+//               groups replace it only when strictly greater).  The even and
+//               odd parts of a chunk are scanned separately; each yields the
+//               key (S, then the lower group start), S = 2 max - parity.
+//               The four lane groups are merged and the chunk's key is
+//               written to part[chunk][t].
+// fbnn_final    per target: the maximum key over all chunks names the first
+//               group of TG tiles (in the partitioned order of the winning
+//               class) that holds a nearest neighbour; its 16 TG rows are
+//               re-measured exactly from the bytes and the smallest
+//               (distance, original index) wins.  Partitioned order is
+//               original order inside a class, and rows of the other class
+//               cannot tie, so that is the lowest-index nearest neighbour.
 //
 // Compile-time constants (FB_<name>):
 //   problem  T (targets)  M (neighbours)  D (bytes per patch, D % 16 == 0)
 //   scan     NT (16-target tiles per wave)  WV (waves per workgroup)
-//            CH (neighbour tiles per chunk)  PF (load the next tile first)
-//            XCDMAP (XCD-aware workgroup order)
-//   final    FW (waves per workgroup)
+//            CH (tiles per chunk)  TG (tiles per tracking group)
+//            PF (load the next tile first)  XCDMAP (XCD-aware order)
+//   final    FW (waves per workgroup)  TG  NCHK (chunks)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -48,22 +66,27 @@
 #define M FB_M
 #define D FB_D
 #define MT ((M + 15) / 16)
+#define MT1 (MT + 1)                 // tiles of the partitioned order (two padded classes)
+#define NB ((M + 63) / 64)           // 64-row blocks of the partition
 #define KB ((D + 63) / 64)
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-// Sentinel score term of padding rows: -2^28 is below any real score, which
-// stays inside (-2^25, 2^25) for D <= 512.
-#define NN_PAD_NORM (1 << 28)
+// Score term of padding rows: -2^28 keeps them below every real half score,
+// which lies in (-2^24, 2^24) for D <= 512.
+#define NN_PAD_TERM (-(1 << 28))
+
+// Header words in the workspace: [0] even rows, [1] first tile of the odd class.
+#define HDR_EVEN 0
+#define HDR_KODD 1
 
 #ifdef FB_NN_NORMS
-// Four lanes per row, 16 bytes each per 64-byte step, then a 4-lane sum.
 extern "C" __global__ void __launch_bounds__(256)
-fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ cneg)
+fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ nn, int* __restrict__ cnt)
 {
-    const long g = (long)blockIdx.x * 256 + threadIdx.x;
-    const long row = g >> 2;
-    const int q = (int)(g & 3);
+    __shared__ int wsum[4];
+    const long row = (long)blockIdx.x * 64 + (threadIdx.x >> 2);
+    const int q = threadIdx.x & 3;
     int s = 0;
     if (row < M) {
 #pragma unroll
@@ -82,7 +105,83 @@ fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ cneg)
     }
     s += __shfl_xor(s, 1);
     s += __shfl_xor(s, 2);
-    if (q == 0 && row < (long)MT * 16) cneg[row] = row < M ? -s : -NN_PAD_NORM;
+    if (q == 0 && row < M) nn[row] = s;
+    const unsigned long long even = __ballot(q == 0 && row < M && (s & 1) == 0);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(even);
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+#endif
+
+#ifdef FB_NN_OFFSETS
+// One workgroup of 1024 threads; cnt[] becomes the exclusive prefix sum.
+extern "C" __global__ void __launch_bounds__(1024)
+fbnn_offsets(int* __restrict__ cnt, int* __restrict__ hdr, int* __restrict__ perm, int* __restrict__ cneg)
+{
+    __shared__ int sc[1024];
+    __shared__ int tot;
+    const int tid = threadIdx.x;
+    const long per = ((long)NB + 1023) / 1024;
+    const long b0 = tid * per, b1 = (b0 + per < NB) ? b0 + per : NB;
+    int s = 0;
+    for (long b = b0; b < b1; ++b) s += cnt[b];
+    sc[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {      // inclusive scan of the segment sums
+        const int v = tid >= off ? sc[tid - off] : 0;
+        __syncthreads();
+        sc[tid] += v;
+        __syncthreads();
+    }
+    int run = sc[tid] - s;                          // exclusive start of this segment
+    for (long b = b0; b < b1; ++b) {
+        const int v = cnt[b];
+        cnt[b] = run;
+        run += v;
+    }
+    if (tid == 1023) tot = sc[1023];
+    __syncthreads();
+    const int me = tot, mo = M - me;
+    const int kodd = (me + 15) / 16;
+    if (tid == 0) {
+        hdr[HDR_EVEN] = me;
+        hdr[HDR_KODD] = kodd;
+    }
+    // padding of the even class's last tile and everything after the odd class
+    for (int p = me + tid; p < kodd * 16; p += 1024) {
+        perm[p] = -1;
+        cneg[p] = NN_PAD_TERM;
+    }
+    for (long p = (long)kodd * 16 + mo + tid; p < (long)MT1 * 16; p += 1024) {
+        perm[p] = -1;
+        cneg[p] = NN_PAD_TERM;
+    }
+}
+#endif
+
+#ifdef FB_NN_SCATTER
+// One wave per 64-row block, one row per lane.
+extern "C" __global__ void __launch_bounds__(64)
+fbnn_scatter(const int* __restrict__ nn, const int* __restrict__ off, const int* __restrict__ hdr,
+             int* __restrict__ perm, int* __restrict__ cneg)
+{
+    const int lane = threadIdx.x;
+    const long b = blockIdx.x;
+    const long row = b * 64 + lane;
+    const bool valid = row < M;
+    const int v = valid ? nn[row] : 0;
+    const bool even = valid && (v & 1) == 0, odd = valid && (v & 1) != 0;
+    const unsigned long long me = __ballot(even), mo = __ballot(odd);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const long e0 = off[b];
+    const long o0 = b * 64 - e0;                    // odd rows in earlier blocks
+    long pos = 0;
+    if (even) pos = e0 + __popcll(me & below);
+    if (odd) pos = (long)hdr[HDR_KODD] * 16 + o0 + __popcll(mo & below);
+    if (valid) {
+        perm[pos] = (int)row;
+        cneg[pos] = -(v >> 1);
+    }
 }
 #endif
 
@@ -90,12 +189,13 @@ fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ cneg)
 #define NT FB_NT
 #define WV FB_WV
 #define CH FB_CH
+#define TG FB_TG
 #define PF FB_PF
 #define XCDMAP FB_XCDMAP
 #define TPW (NT * 16)
 #define TPG (WV * TPW)
 #define TB ((T + TPG - 1) / TPG)
-#define NCHK ((MT + CH - 1) / CH)
+#define NCHK ((MT1 + CH - 1) / CH)
 
 // 16 bytes of a row, centred (XOR 0x80 per byte); zero past the patch end.
 __device__ __forceinline__ i32x4 ld_centred(const unsigned char* p, bool inside)
@@ -107,10 +207,11 @@ __device__ __forceinline__ i32x4 ld_centred(const unsigned char* p, bool inside)
 
 // At least two waves per SIMD caps the kernel at 256 VGPRs, which lets the
 // compiler keep the accumulators in ordinary VGPRs (no accumulator-register
-// copies before the per-tile maximum).
+// copies before the running maximum).
 extern "C" __global__ void __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(2)))
 fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict__ nb,
-          const int* __restrict__ cneg, unsigned long long* __restrict__ part)
+          const int* __restrict__ perm, const int* __restrict__ cneg, const int* __restrict__ hdr,
+          unsigned long long* __restrict__ part)
 {
     int lin = blockIdx.x;
 #if XCDMAP
@@ -137,89 +238,122 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
         }
     }
 
-    int mx[NT], st[NT];
+    unsigned long long best[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        mx[nt] = -2147483647 - 1;
-        st[nt] = 0;
-    }
+    for (int nt = 0; nt < NT; ++nt) best[nt] = 0ull;
 
-    const int k_begin = chunk * CH;
-    const int k_end = (k_begin + CH < MT) ? k_begin + CH : MT;
-
-    // Neighbour tile k: A operand (row = neighbour) and the -|n|^2 start
-    // values of this lane's four accumulator rows.
-    i32x4 af[KB], ci;
-    auto load_tile = [&](int k, i32x4* a, i32x4& c) {
-        int row = k * 16 + col;
-        row = row < M ? row : M - 1;        // padding rows lose on their sentinel
+    // Tile k of the partitioned order: this lane's A row (a neighbour,
+    // gathered; padding rows read row 0 and lose on their score term) and
+    // the start values of its four accumulator rows.
+    auto load_rows = [&](int pidx, i32x4* a) {
+        const long row = pidx < 0 ? 0 : pidx;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const int k0 = kb * 64 + grp * 16;
-            a[kb] = ld_centred(nb + (long)row * D + k0, k0 < D);
+            a[kb] = ld_centred(nb + row * D + k0, k0 < D);
         }
-        c = *(const i32x4*)(cneg + k * 16 + grp * 4);
     };
-    load_tile(k_begin, af, ci);
+    auto perm_at = [&](int k) { return perm[(long)k * 16 + col]; };
+    auto cneg_at = [&](int k) { return *(const i32x4*)(cneg + (long)k * 16 + grp * 4); };
 
-#pragma unroll 1
-    for (int k = k_begin; k < k_end; ++k) {
-#if PF
-        i32x4 an[KB], cn;
-        if (k + 1 < k_end) load_tile(k + 1, an, cn);
-#endif
-        i32x4 acc[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[nt] = ci;
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass)
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[kb], bf[nt][kb], acc[nt], 0, 0, 0);
+    // Scan tiles [k0, k1) of one parity class (cls 0 even, 1 odd).
+    auto scan_range = [&](int k0, int k1, int cls) {
+        if (k0 >= k1) return;
+        int mx[NT], st[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            int v = max(max(mx[nt], acc[nt][0]), acc[nt][1]);
-            v = max(max(v, acc[nt][2]), acc[nt][3]);
-            st[nt] = v != mx[nt] ? k : st[nt];
-            mx[nt] = v;
+            mx[nt] = -2147483647 - 1;
+            st[nt] = k0;
         }
+        i32x4 af[KB], ci = cneg_at(k0);
+        load_rows(perm_at(k0), af);
+        int pn = (k0 + 1 < k1) ? perm_at(k0 + 1) : 0;
+#pragma unroll 1
+        for (int g0 = k0; g0 < k1; g0 += TG) {
+            int gm[NT];                      // max(running maximum, this group)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) gm[nt] = mx[nt];
+#pragma unroll
+            for (int j = 0; j < TG; ++j) {
+                const int k = g0 + j;
+                if (k < k1) {
 #if PF
-        if (k + 1 < k_end) {
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) af[kb] = an[kb];
-            ci = cn;
-        }
-#else
-        if (k + 1 < k_end) load_tile(k + 1, af, ci);
+                    i32x4 an[KB], cn;
+                    int pn2 = 0;
+                    if (k + 1 < k1) {
+                        load_rows(pn, an);
+                        cn = cneg_at(k + 1);
+                        if (k + 2 < k1) pn2 = perm_at(k + 2);
+                    }
 #endif
-    }
-
-    // Key = (score mapped to unsigned order) : (~first row of the group), so
-    // the unsigned maximum takes the higher score, then the lower row.
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        unsigned hi = (unsigned)mx[nt] ^ 0x80000000u;
-        unsigned lo = 0xFFFFFFFFu - (unsigned)(st[nt] * 16 + grp * 4);
+                    for (int nt = 0; nt < NT; ++nt) {
+                        i32x4 acc = ci;
 #pragma unroll
-        for (int s = 16; s <= 32; s <<= 1) {
-            const unsigned ohi = (unsigned)__shfl_xor((int)hi, s);
-            const unsigned olo = (unsigned)__shfl_xor((int)lo, s);
-            if (ohi > hi || (ohi == hi && olo > lo)) {
-                hi = ohi;
-                lo = olo;
+                        for (int kb = 0; kb < KB; ++kb)
+                            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[kb], bf[nt][kb], acc, 0, 0, 0);
+                        gm[nt] = max(max(gm[nt], acc[0]), acc[1]);
+                        gm[nt] = max(max(gm[nt], acc[2]), acc[3]);
+                    }
+                    if (k + 1 < k1) {
+#if PF
+#pragma unroll
+                        for (int kb = 0; kb < KB; ++kb) af[kb] = an[kb];
+                        ci = cn;
+                        pn = pn2;
+#else
+                        load_rows(perm_at(k + 1), af);
+                        ci = cneg_at(k + 1);
+#endif
+                    }
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                st[nt] = gm[nt] != mx[nt] ? g0 : st[nt];
+                mx[nt] = gm[nt];
             }
         }
+        // Key = (exact score S mapped to unsigned order) : (~first row of the
+        // group), so the unsigned maximum takes the higher S, then the
+        // earlier group.
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const unsigned hi = (unsigned)(2 * mx[nt] - cls) ^ 0x80000000u;
+            const unsigned lo = 0xFFFFFFFFu - (unsigned)st[nt] * 16u;
+            const unsigned long long key = ((unsigned long long)hi << 32) | lo;
+            best[nt] = key > best[nt] ? key : best[nt];
+        }
+    };
+
+    const int k_begin = chunk * CH;
+    const int k_end = (k_begin + CH < MT1) ? k_begin + CH : MT1;
+    const int kodd = hdr[HDR_KODD];
+    scan_range(k_begin, min(k_end, kodd), 0);
+    scan_range(max(k_begin, kodd), k_end, 1);
+
+    // merge the four lane groups of each target and store the chunk's key
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        unsigned long long key = best[nt];
+#pragma unroll
+        for (int s = 16; s <= 32; s <<= 1) {
+            const unsigned ohi = (unsigned)__shfl_xor((int)(unsigned)(key >> 32), s);
+            const unsigned olo = (unsigned)__shfl_xor((int)(unsigned)key, s);
+            const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+            key = o > key ? o : key;
+        }
         const int t = tb * TPG + wave * TPW + nt * 16 + col;
-        if (grp == 0 && t < T) part[(long)chunk * T + t] = ((unsigned long long)hi << 32) | lo;
+        if (grp == 0 && t < T) part[(long)chunk * T + t] = key;
     }
 }
 #endif
 
 #ifdef FB_NN_FINAL
 #define FW FB_FW
+#define TG FB_TG
 #define NCHK FB_NCHK
+#define CAND (16 * TG)               // rows of one tracking group
 
 __device__ __forceinline__ int sq_dist(const unsigned char* a, const unsigned char* b)
 {
@@ -240,12 +374,16 @@ __device__ __forceinline__ int sq_dist(const unsigned char* a, const unsigned ch
     return s;
 }
 
-// 64 targets per workgroup, one per lane; the FW waves split the chunks.
+// 64 targets per workgroup: first one per lane (the FW waves split the
+// chunks), then the workgroup's threads re-measure the 64 x CAND candidates.
 extern "C" __global__ void __launch_bounds__(FW * 64)
 fbnn_final(const unsigned char* __restrict__ tg, const unsigned char* __restrict__ nb,
-           const unsigned long long* __restrict__ part, int* __restrict__ idx, int* __restrict__ dist)
+           const int* __restrict__ perm, const unsigned long long* __restrict__ part,
+           int* __restrict__ idx, int* __restrict__ dist)
 {
     __shared__ unsigned long long red[FW][64];
+    __shared__ unsigned long long win[64];
+    __shared__ int g0s[64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t = blockIdx.x * 64 + lane;
     unsigned long long key = 0;
@@ -257,24 +395,30 @@ fbnn_final(const unsigned char* __restrict__ tg, const unsigned char* __restrict
         }
     }
     red[wave][lane] = key;
+    if (wave == 0) win[lane] = ~0ull;
     __syncthreads();
-    if (wave != 0 || t >= T) return;
+    if (wave == 0) {
 #pragma unroll
-    for (int w = 1; w < FW; ++w) key = red[w][lane] > key ? red[w][lane] : key;
-    const unsigned start = 0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull);
-    int best = 2147483647, bi = -1;
-#pragma unroll 1
-    for (int r = 0; r < 4; ++r) {
-        const unsigned row = start + r;
-        if (row < (unsigned)M) {
-            const int e = sq_dist(tg + (long)t * D, nb + (long)row * D);
-            if (e < best) {
-                best = e;
-                bi = (int)row;
+        for (int w = 1; w < FW; ++w) key = red[w][lane] > key ? red[w][lane] : key;
+        g0s[lane] = (int)((0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull)) >> 4);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * CAND; e += FW * 64) {
+        const int tl = e / CAND, j = e % CAND;
+        const int tt = blockIdx.x * 64 + tl;
+        const long pos = (long)g0s[tl] * 16 + j;
+        if (tt < T && pos < (long)MT1 * 16) {
+            const int orig = perm[pos];
+            if (orig >= 0) {
+                const int d = sq_dist(tg + (long)tt * D, nb + (long)orig * D);
+                atomicMin(&win[tl], ((unsigned long long)(unsigned)d << 32) | (unsigned)orig);
             }
         }
     }
-    idx[t] = bi;
-    dist[t] = best;
+    __syncthreads();
+    if (wave == 0 && t < T) {
+        idx[t] = (int)(unsigned)(win[lane] & 0xFFFFFFFFull);
+        dist[t] = (int)(unsigned)(win[lane] >> 32);
+    }
 }
 #endif

@@ -99,11 +99,11 @@ class NNPlan:
         nat.check(self.lib.fbnn_plan_enable_timing(self.handle, 1 if on else 0))
 
     def read_timing(self, reset=True):
-        """{'norms'|'scan'|'final': (total ms, launches)}"""
+        """{'prepare'|'scan'|'final': (total ms, searches)}"""
         ms = (ctypes.c_double * 3)()
         calls = (ctypes.c_int64 * 3)()
         nat.check(self.lib.fbnn_plan_read_timing(self.handle, ms, calls, 1 if reset else 0))
-        return {k: (ms[i], calls[i]) for i, k in enumerate(("norms", "scan", "final"))}
+        return {k: (ms[i], calls[i]) for i, k in enumerate(("prepare", "scan", "final"))}
 
     def close(self) -> None:
         if getattr(self, "handle", None):

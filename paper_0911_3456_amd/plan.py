@@ -32,11 +32,13 @@ def _check_tensor(t: torch.Tensor, shape, name: str) -> None:
 class Plan:
     """A compiled plan for one problem shape (see include/fbcorr.h)."""
 
-    def __init__(self, batch, H, W, D, N, fh, fw, precision="fp32", algo="auto", device=None):
+    def __init__(self, batch, H, W, D, N, fh, fw, precision="fp32", algo="auto", device=None,
+                 overlap_backward=False):
         self.lib = nat.load()
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    torch.device(device).index or 0)
-        self.desc = nat.make_desc(batch, H, W, D, N, fh, fw, precision, algo)
+        self.desc = nat.make_desc(batch, H, W, D, N, fh, fw, precision, algo,
+                                  nat.FLAG_OVERLAP_BACKWARD if overlap_backward else 0)
         self.shape = (batch, H, W, D, N, fh, fw)
         self.precision = precision
         h = ctypes.c_void_p()

@@ -94,6 +94,10 @@ def test_invalid_descriptors_map_to_status():
     with pytest.raises(FbcorrError) as e:
         codegen(make_desc(1, 8, 8, 4, 4, 3, 3, precision="bf16", algo="direct"))
     assert e.value.status_name == "FBCORR_ERR_UNSUPPORTED"
+    with pytest.raises(FbcorrError) as e:
+        codegen(make_desc(1, 8, 8, 4, 4, 3, 3, flags=2))
+    assert e.value.status_name == "FBCORR_ERR_INVALID_ARGUMENT"
+    assert codegen(make_desc(1, 8, 8, 4, 4, 3, 3, flags=1))[0]     # FBCORR_FLAG_OVERLAP_BACKWARD
 
 
 def test_bad_configs_rejected_before_compiling():

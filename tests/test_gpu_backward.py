@@ -221,15 +221,17 @@ def test_differentiation_workload():
         assert oracle.normalised_error(dw[n:n + 1], rw, sw)[0] <= TOL
 
 
-def test_concurrent_backward_from_two_threads():
+@pytest.mark.parametrize("overlap", [False, True])
+def test_concurrent_backward_from_two_threads(overlap):
     """One plan used from two host threads on two streams with separate
-    workspaces (the documented concurrency contract): both results exact."""
+    workspaces (the documented concurrency contract): both results exact,
+    with the gradients in sequence or overlapped on the side stream."""
     need_gpu()
     import threading
     import torch
     from paper_0911_3456_amd import Plan
     s = wl.Shape(2, 60, 70, 8, 64, 7, 7)
-    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw)
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, overlap_backward=overlap)
     need = plan.workspace_size(1)
     data, refs, outs = [], [], [None, None]
     for t in range(2):
@@ -265,3 +267,22 @@ def test_concurrent_backward_from_two_threads():
     for t in range(2):
         np.testing.assert_array_equal(outs[t][0], refs[t][0].astype(np.float32))
         np.testing.assert_array_equal(outs[t][1], refs[t][1].astype(np.float32))
+
+
+def test_overlapped_backward_matches_sequential():
+    """The side-stream overlap changes only the schedule: dx and dw are bit
+    for bit those of the sequential path."""
+    need_gpu()
+    from paper_0911_3456_amd import Plan
+    wk = wl.WORKLOADS["fp32"]
+    s = wk.shape
+    x, w, rng = wl.draw_single(s, wk.seed)
+    g = wl.draw_grad(s, rng)
+    xt, wt, gt = to_dev(x, w, g)
+    res = []
+    for overlap in (False, True):
+        plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, overlap_backward=overlap)
+        dx, dw = plan.backward(xt, wt, gt)
+        res.append((host(dx), host(dw)))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(res[0][1], res[1][1])

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 # Explicit configurations the tests install (validated on the host by
 # tests/test_abi_nn.py before any GPU run).
-NN_CFGS = ["nt=1 wv=1 ch=1 pf=0", "nt=2 wv=4 ch=3 pf=1", "nt=4 wv=4 ch=64 pf=1", "nt=8 wv=2 ch=1000 pf=1",
+NN_CFGS = ["nt=1 wv=1 ch=1 pf=0 tg=1", "nt=2 wv=4 ch=3 pf=1 tg=2", "nt=4 wv=4 ch=64 pf=1 tg=4", "nt=8 wv=2 ch=1000 pf=1",
            "nt=4 wv=8 ch=7 pf=0 xcd=0", "nt=1 wv=2 ch=2 fw=1", "nt=8 wv=1 ch=16 fw=16"]
 
 
@@ -179,10 +179,40 @@ def test_timing_and_config_roundtrip():
     for _ in range(3):
         _search(t, n, plan=plan)
     tm = plan.read_timing()
-    assert all(tm[k][1] == 3 and tm[k][0] > 0 for k in ("norms", "scan", "final"))
+    assert all(tm[k][1] == 3 and tm[k][0] > 0 for k in ("prepare", "scan", "final"))
     before = plan.get_config()
     with pytest.raises(FbcorrError):
         plan.set_config("nt=99")
     assert plan.get_config() == before
     plan.set_config("nt=2 ch=4")
     assert "nt=2" in plan.get_config() and "ch=4" in plan.get_config()
+
+
+def test_parity_classes():
+    """The scan splits the neighbours by the parity of their centred norm;
+    nearest rows that sit in either class, one class empty, and neighbours
+    one unit of distance apart across the classes."""
+    need_gpu()
+    base = np.full(64, 128, np.uint8)
+
+    def row(*bumps):
+        r = base.copy()
+        for k, v in bumps:
+            r[k] = v
+        return r
+
+    t = np.stack([base, row((0, 200)), row((5, 129), (6, 129))])
+    cases = [
+        # odd-norm row nearest (distance 3), even-norm row at 4 behind it
+        [row((0, 130)), row((1, 129), (2, 129), (3, 129)), row((0, 129), (1, 130))],
+        # even-norm row nearest (distance 2), odd at 3
+        [row((1, 129), (2, 129), (3, 129)), row((4, 129), (9, 129)), row((0, 129), (1, 130))],
+        # only even norms, only odd norms
+        [row((0, 130)), row((1, 130)), row((2, 126))],
+        [row((0, 129)), row((1, 131)), row((2, 127))],
+    ]
+    for cfg in (None, "tg=2 ch=1", "tg=4 nt=1 wv=1"):
+        for n in cases:
+            n = np.stack(n * 7)               # repeats: ties to the first copy
+            idx, dist, _ = _search(t, n, cfg)
+            _assert_exact(t, n, idx, dist, "parity %s" % cfg)
