@@ -23,8 +23,8 @@ namespace {
 constexpr int kScoreTargets = 2048;   // workgroups the default chunking aims for
 
 struct NNGeom {
-    int nt = 0, wv = 0, ch = 0, fw = 0, tg = 0;
-    long tpg = 0, tb = 0, mt1 = 0, nblk = 0, nchk = 0;
+    int nt = 0, wv = 0, ch = 0, fw = 0, tg = 0, bt = 0, split = 0;
+    long tpg = 0, tb = 0, mts = 0, nblk = 0, nchk = 0;
     LaunchGeom norms, offsets, scatter, scan, fin;
     size_t off_hdr = 0, off_nn = 0, off_cnt = 0, off_perm = 0, off_cneg = 0, off_part = 0, ws_bytes = 0;
 };
@@ -85,21 +85,30 @@ Config heuristic(const fbnn_desc& d) {
     const int nt = std::max(1, std::min(8, 16 / kb));   // target fragments stay <= 64 VGPRs
     c.algo = "nn";
     c.v["nt"] = nt;
-    c.v["wv"] = 8;
-    c.v["pf"] = 1;
-    c.v["tg"] = 1;
+    c.v["wv"] = 4;
+    c.v["bt"] = 4;
+    c.v["tg"] = 2;
+    // the parity partition costs three small kernels; it pays off once the
+    // scan is long enough
+    c.v["split"] = d.n_neighbors >= 65536 ? 1 : 0;
     c.v["xcd"] = 1;
     c.v["fw"] = 4;
-    c.v["ch"] = chunk_for(d, nt, 8, kScoreTargets);
+    c.v["ch"] = chunk_for(d, nt, 4, kScoreTargets);
     return c;
 }
 
-Config default_cfg(const fbnn_desc& d, const std::string& arch) {
+bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBuild& b, std::string& err);
+
+// The tuning database's entry when there is one and it still builds (an
+// entry written for another version of the kernels is ignored), else the
+// heuristic.
+Config default_cfg(const fbnn_desc& d, const DeviceInfo& di) {
     Config c = heuristic(d);
     std::string text, err;
-    if (tuning_db_lookup_key(db_key(arch, d), text)) {
+    if (tuning_db_lookup_key(db_key(di.arch, d), text)) {
         Config t = c;
-        if (parse_config(text, t, err) && t.algo == "nn") c = t;
+        NNBuild probe;
+        if (parse_config(text, t, err) && make_build(d, t, di, probe, err)) c = t;
     }
     return c;
 }
@@ -109,7 +118,8 @@ void opt(std::vector<std::string>& o, const char* k, long v) {
 }
 
 bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBuild& b, std::string& err) {
-    static const std::set<std::string> known = {"nt", "wv", "ch", "pf", "tg", "xcd", "fw", "inject_error"};
+    static const std::set<std::string> known = {"nt", "wv", "ch", "bt", "tg", "split", "xcd", "fw",
+                                                "inject_error"};
     if (c.algo != "nn") { err = "algo must be nn"; return false; }
     for (auto& kv : c.v)
         if (!known.count(kv.first)) { err = "unknown key '" + kv.first + "' for algo=nn"; return false; }
@@ -119,22 +129,28 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     g.ch = c.get("ch");
     g.fw = c.get("fw");
     g.tg = c.get("tg");
-    const int pf = c.get("pf"), xcd = c.get("xcd");
+    g.bt = c.get("bt");
+    g.split = c.get("split");
+    const int xcd = c.get("xcd");
     const int kb = (d.dim + 63) / 64;
     if (g.nt < 1 || g.nt > 8) { err = "nt must be in [1, 8]"; return false; }
     if (g.nt * kb > 16) { err = "nt * ceil(dim/64) > 16 (target fragments would not fit in registers)"; return false; }
     if (g.wv < 1 || g.wv * 64 > di.max_threads) { err = "wv out of range"; return false; }
     if (g.fw < 1 || g.fw > 16) { err = "fw must be in [1, 16]"; return false; }
     if (g.ch < 1) { err = "ch must be >= 1"; return false; }
+    if (g.bt != 1 && g.bt != 2 && g.bt != 4 && g.bt != 8 && g.bt != 16) { err = "bt must be 1, 2, 4, 8 or 16"; return false; }
     if (g.tg != 1 && g.tg != 2 && g.tg != 4) { err = "tg must be 1, 2 or 4"; return false; }
-    if (pf < 0 || pf > 1 || xcd < 0 || xcd > 1) { err = "pf and xcd are 0 or 1"; return false; }
+    if (g.bt % g.tg != 0) { err = "tg must divide bt"; return false; }
+    if (g.split < 0 || g.split > 1 || xcd < 0 || xcd > 1) { err = "split and xcd are 0 or 1"; return false; }
+    const long lds = 2L * g.bt * 16 * (d.dim + 16) + 2L * g.bt * 16 * 4;
+    if (lds > di.lds_per_block) { err = "LDS batch exceeds the device limit"; return false; }
     const long T = d.n_targets;
     g.tpg = (long)g.wv * g.nt * 16;
     g.tb = std::max(1L, cdiv(T, g.tpg));
-    g.mt1 = cdiv(d.n_neighbors, 16) + 1;       // both parity classes padded to whole tiles
+    g.mts = cdiv(d.n_neighbors, 16) + g.split;   // with the partition: two classes padded to whole tiles
     g.nblk = cdiv(d.n_neighbors, 64);
-    g.ch = (int)std::min<long>(g.ch, g.mt1);
-    g.nchk = cdiv(g.mt1, g.ch);
+    g.ch = (int)std::min<long>(g.ch, g.mts);
+    g.nchk = cdiv(g.mts, g.ch);
     if (g.tb * g.nchk >= (1L << 31)) { err = "too many scan workgroups"; return false; }
     g.norms = LaunchGeom{(int)g.nblk, 1, 256, 0};
     g.offsets = LaunchGeom{1, 1, 1024, 0};
@@ -143,10 +159,12 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     g.fin = LaunchGeom{(int)std::max(1L, cdiv(T, 64)), 1, g.fw * 64, 0};
     size_t off = 0;
     g.off_hdr = off;  off += 256;
-    g.off_nn = off;   off += align256((size_t)d.n_neighbors * 4);
-    g.off_cnt = off;  off += align256((size_t)g.nblk * 4);
-    g.off_perm = off; off += align256((size_t)g.mt1 * 16 * 4);
-    g.off_cneg = off; off += align256((size_t)g.mt1 * 16 * 4);
+    if (g.split) {
+        g.off_nn = off;   off += align256((size_t)d.n_neighbors * 4);
+        g.off_cnt = off;  off += align256((size_t)g.nblk * 4);
+        g.off_perm = off; off += align256((size_t)g.mts * 16 * 4);
+    }
+    g.off_cneg = off; off += align256((size_t)g.mts * 16 * 4);
     g.off_part = off; off += align256((size_t)g.nchk * (size_t)std::max(T, 1L) * 8);
     g.ws_bytes = off;
     b.cfg = c;
@@ -161,18 +179,22 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
         opt(ks.options, "T", std::max(T, 1L));
         opt(ks.options, "M", d.n_neighbors);
         opt(ks.options, "D", d.dim);
+        opt(ks.options, "SPLIT", g.split);
         if (c.get("inject_error")) ks.options.push_back("-DFB_INJECT_ERROR");
     };
+    for (auto& ks : b.ks) ks = KernelSource();
     base(b.ks[K_NORMS], "fbnn_norms", "NN_NORMS");
-    base(b.ks[K_OFFSETS], "fbnn_offsets", "NN_OFFSETS");
-    base(b.ks[K_SCATTER], "fbnn_scatter", "NN_SCATTER");
+    if (g.split) {
+        base(b.ks[K_OFFSETS], "fbnn_offsets", "NN_OFFSETS");
+        base(b.ks[K_SCATTER], "fbnn_scatter", "NN_SCATTER");
+    }
     base(b.ks[K_SCAN], "fbnn_scan", "NN_SCAN");
     auto& sc = b.ks[K_SCAN].options;
     opt(sc, "NT", g.nt);
     opt(sc, "WV", g.wv);
     opt(sc, "CH", g.ch);
+    opt(sc, "BT", g.bt);
     opt(sc, "TG", g.tg);
-    opt(sc, "PF", pf);
     opt(sc, "XCDMAP", xcd);
     base(b.ks[K_FINAL], "fbnn_final", "NN_FINAL");
     opt(b.ks[K_FINAL].options, "FW", g.fw);
@@ -183,6 +205,7 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
 
 fbcorr_status load_build(NNPlan* p, const NNBuild& b, Kernel* k) {
     for (int i = 0; i < K_COUNT; ++i) {
+        if (b.ks[i].name.empty()) continue;      // not part of this configuration
         fbcorr_status st = load_kernel(b.ks[i], p->device, k[i]);
         if (st != FBCORR_OK) return st;
     }
@@ -216,17 +239,23 @@ fbcorr_status run(const NNBuild& b, const Kernel* k, const uint8_t* tg, const ui
     unsigned long long* part = (unsigned long long*)(base + b.g.off_part);
     fbcorr_status st;
     if (ev) hipEventRecord(ev[0], s);
-    {
-        void* args[] = {&nb, &nn, &cnt};
+    if (b.g.split) {
+        {
+            void* args[] = {&nb, &nn, &cnt};
+            if ((st = launch(k[K_NORMS], b.g.norms, s, args))) return st;
+        }
+        {
+            void* args[] = {&cnt, &hdr, &perm, &cneg};
+            if ((st = launch(k[K_OFFSETS], b.g.offsets, s, args))) return st;
+        }
+        {
+            void* args[] = {&nn, &cnt, &hdr, &perm, &cneg};
+            if ((st = launch(k[K_SCATTER], b.g.scatter, s, args))) return st;
+        }
+    } else {
+        int* unused = nullptr;
+        void* args[] = {&nb, &cneg, &unused};       // start values -|n|^2 straight into cneg
         if ((st = launch(k[K_NORMS], b.g.norms, s, args))) return st;
-    }
-    {
-        void* args[] = {&cnt, &hdr, &perm, &cneg};
-        if ((st = launch(k[K_OFFSETS], b.g.offsets, s, args))) return st;
-    }
-    {
-        void* args[] = {&nn, &cnt, &hdr, &perm, &cneg};
-        if ((st = launch(k[K_SCATTER], b.g.scatter, s, args))) return st;
     }
     if (ev) hipEventRecord(ev[1], s);
     {
@@ -258,18 +287,20 @@ std::vector<Config> candidates(const fbnn_desc& d) {
     std::vector<Config> out;
     std::set<std::string> seen;
     const int kb = (d.dim + 63) / 64;
-    for (int nt : {2, 4, 8})
-        for (int wv : {2, 4, 8})
-            for (long wgs : {512L, 1024L, 2048L, 4096L})
-                for (int pf : {0, 1})
-                    for (int tg : {1, 2}) {
+    static const int btg[][2] = {{2, 1}, {4, 2}, {8, 2}, {8, 4}};
+    for (int split : {0, 1})
+        for (int nt : {2, 4, 8})
+            for (int wv : {2, 4, 8})
+                for (long wgs : {512L, 1024L, 2048L, 4096L})
+                    for (auto& bg : btg) {
                         if (nt * kb > 16) continue;
                         Config c;
                         c.algo = "nn";
                         c.v["nt"] = nt;
                         c.v["wv"] = wv;
-                        c.v["pf"] = pf;
-                        c.v["tg"] = tg;
+                        c.v["bt"] = bg[0];
+                        c.v["tg"] = bg[1];
+                        c.v["split"] = split;
                         c.v["xcd"] = 1;
                         c.v["fw"] = 4;
                         c.v["ch"] = chunk_for(d, nt, wv, wgs);
@@ -314,7 +345,7 @@ fbcorr_status fbnn_plan(const fbnn_desc* desc, int device, fbnn_plan_t* out) {
     st = device_info(device, p->dev);
     if (st != FBCORR_OK) return st;
     DeviceGuard g(device);
-    st = install(p.get(), default_cfg(*desc, p->dev.arch));
+    st = install(p.get(), default_cfg(*desc, p->dev));
     if (st != FBCORR_OK) return st;
     *out = reinterpret_cast<fbnn_plan_t>(p.release());
     return FBCORR_OK;
@@ -462,13 +493,14 @@ fbcorr_status fbnn_compile_check(const fbnn_desc* desc, const char* cfg, const c
     fbcorr_status st = validate(desc);
     if (st != FBCORR_OK) return st;
     const DeviceInfo di = offline(arch);
-    Config c = default_cfg(*desc, di.arch);
+    Config c = default_cfg(*desc, di);
     std::string err;
     FBC_RETURN_IF(cfg && !parse_config(cfg, c, err), FBCORR_ERR_INVALID_ARGUMENT, err);
     NNBuild b;
     FBC_RETURN_IF(!make_build(*desc, c, di, b, err), FBCORR_ERR_UNSUPPORTED, err);
     size_t total = 0;
     for (const KernelSource& ks : b.ks) {
+        if (ks.name.empty()) continue;
         std::shared_ptr<const std::vector<char>> code;
         st = compile_cached(ks, di.arch, code);
         if (st != FBCORR_OK) return st;
@@ -578,6 +610,7 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
             for (size_t i; (i = next.fetch_add(1)) < builds.size();) {
                 std::shared_ptr<const std::vector<char>> code;
                 for (const KernelSource& ks : builds[i].ks) {
+                    if (ks.name.empty()) continue;
                     res[i] = compile_cached(ks, p->dev.arch, code);
                     if (res[i] != FBCORR_OK) break;
                 }

@@ -11,48 +11,51 @@
 //
 //   S(t, m) = 2 t.n_m - |n_m|^2          (= |t|^2 - dist(t, m)).
 //
-// 2t does not fit in int8, so the matrix cores compute the half score
-// s(t, m) = t.n_m - floor(|n_m|^2 / 2) in one pass, and S = 2s - (|n_m|^2
-// odd).  Inside a set of neighbours whose |n|^2 have the same parity, s
-// orders them exactly as S does; two neighbours of different parity never
-// have equal S.  The neighbours are therefore partitioned, stably, into an
-// even class and an odd class, each padded to whole 16-row tiles, and the
-// scan runs on the partitioned order:
+// 2t does not fit in int8.  Two exact ways round it, chosen by SPLIT:
 //
-// fbnn_norms    |n_m|^2 for every row (4 lanes per row) and the number of
-//               even rows of each 64-row block.
-// fbnn_offsets  one workgroup: exclusive prefix sum of the block counts
-//               (in place), the class sizes, and the padding entries
-//               (index -1, score term far below any real score).
-// fbnn_scatter  perm[pos] = m and cneg[pos] = -floor(|n_m|^2 / 2), with pos
-//               the row's place in its class (stable: lane order inside a
-//               block, blocks in order); the odd class starts at the first
-//               tile after the even class.
-// fbnn_scan     one workgroup = a block of targets x a chunk of CH tiles of
-//               the partitioned order.  A v_mfma_i32_16x16x64_i8 product of a
-//               tile (rows = neighbours, gathered through perm) with 16
-//               targets (columns), started from the rows' cneg values, gives
-//               s exactly in int32.  Lane l holds target l%16 against rows
-//               4(l/16)..+3 of the tile and keeps a running maximum over
-//               groups of TG tiles and the first group reaching it (later
-//               groups replace it only when strictly greater).  The even and
-//               odd parts of a chunk are scanned separately; each yields the
-//               key (S, then the lower group start), S = 2 max - parity.
-//               The four lane groups are merged and the chunk's key is
-//               written to part[chunk][t].
-// fbnn_final    per target: the maximum key over all chunks names the first
-//               group of TG tiles (in the partitioned order of the winning
-//               class) that holds a nearest neighbour; its 16 TG rows are
-//               re-measured exactly from the bytes and the smallest
-//               (distance, original index) wins.  Partitioned order is
-//               original order inside a class, and rows of the other class
-//               cannot tie, so that is the lowest-index nearest neighbour.
+//  SPLIT = 0  the matrix cores run twice over the same operands from a start
+//             value of -|n|^2, which gives S itself.
+//  SPLIT = 1  one pass gives the half score s = t.n - floor(|n|^2 / 2), and
+//             S = 2s - (|n|^2 odd).  Inside a set of neighbours whose |n|^2
+//             have the same parity, s orders them as S does, and neighbours
+//             of different parity never have equal S.  The neighbours are
+//             partitioned, stably, into an even and an odd class, each padded
+//             to whole 16-row tiles, and scanned in that order.
+//
+// fbnn_norms    |n_m|^2 of every row (4 lanes per row).  SPLIT = 0: the start
+//               values -|n|^2 (a sentinel far below any real score for the
+//               padding rows of the last tile).  SPLIT = 1: the norms and the
+//               number of even norms in each 64-row block.
+// fbnn_offsets  (SPLIT = 1) one workgroup: exclusive prefix sum of the block
+//               counts (in place), the class sizes, and the padding entries.
+// fbnn_scatter  (SPLIT = 1) perm[pos] = m and cneg[pos] = -floor(|n_m|^2/2)
+//               at the row's place in its class (lane order inside a block,
+//               blocks in order); the odd class starts on a new tile.
+// fbnn_scan     one workgroup = a block of targets x a chunk of CH tiles.
+//               Batches of BT tiles are staged once per workgroup in LDS
+//               (double-buffered, centred on the way in) and shared by its
+//               WV waves.  A v_mfma_i32_16x16x64_i8 product of a tile (rows
+//               = neighbours) with 16 targets (columns), started from the
+//               rows' score terms, gives the (half) score in int32 exactly.
+//               Lane l holds target l%16 against rows 4(l/16)..+3 of a tile;
+//               it keeps a running maximum over groups of TG tiles and the
+//               first group reaching it (a later group replaces it only when
+//               strictly greater).  Per scanned range (SPLIT = 1: the even
+//               and the odd part of the chunk) the key is (S, then the lower
+//               group start); the four lane groups are merged and the chunk's
+//               key is written to part[chunk][t].
+// fbnn_final    per target: the largest key over all chunks names the first
+//               group of TG tiles holding a nearest neighbour (in scan order,
+//               which is index order inside a class); its 16 TG rows are
+//               re-measured from the bytes and the smallest (distance,
+//               index) wins: the lowest-index nearest neighbour.
 //
 // Compile-time constants (FB_<name>):
 //   problem  T (targets)  M (neighbours)  D (bytes per patch, D % 16 == 0)
+//   method   SPLIT
 //   scan     NT (16-target tiles per wave)  WV (waves per workgroup)
-//            CH (tiles per chunk)  TG (tiles per tracking group)
-//            PF (load the next tile first)  XCDMAP (XCD-aware order)
+//            CH (tiles per chunk)  BT (tiles per LDS batch)
+//            TG (tiles per tracking group, divides BT)  XCDMAP
 //   final    FW (waves per workgroup)  TG  NCHK (chunks)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
@@ -65,18 +68,24 @@
 #define T FB_T
 #define M FB_M
 #define D FB_D
+#define SPLIT FB_SPLIT
 #define MT ((M + 15) / 16)
-#define MT1 (MT + 1)                 // tiles of the partitioned order (two padded classes)
-#define NB ((M + 63) / 64)           // 64-row blocks of the partition
+#define NB ((M + 63) / 64)           // 64-row blocks
 #define KB ((D + 63) / 64)
+#if SPLIT
+#define MTS (MT + 1)                 // tiles of the partitioned order (two padded classes)
+#else
+#define MTS MT
+#endif
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-// Score term of padding rows: -2^28 keeps them below every real half score,
-// which lies in (-2^24, 2^24) for D <= 512.
+// Score term of padding rows: -2^28 keeps them below every real score, which
+// lies in (-2^25, 2^25) for D <= 512 (half scores in (-2^24, 2^24)).
 #define NN_PAD_TERM (-(1 << 28))
 
-// Header words in the workspace: [0] even rows, [1] first tile of the odd class.
+// Header words in the workspace (SPLIT = 1): [0] even rows, [1] first tile of
+// the odd class.
 #define HDR_EVEN 0
 #define HDR_KODD 1
 
@@ -105,11 +114,18 @@ fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ nn, int* __re
     }
     s += __shfl_xor(s, 1);
     s += __shfl_xor(s, 2);
+#if SPLIT
     if (q == 0 && row < M) nn[row] = s;
     const unsigned long long even = __ballot(q == 0 && row < M && (s & 1) == 0);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(even);
     __syncthreads();
     if (threadIdx.x == 0) cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#else
+    // nn is the start-value array here: -|n|^2, sentinel past the last row
+    if (q == 0 && row < (long)MT * 16) nn[row] = row < M ? -s : NN_PAD_TERM;
+    (void)cnt;
+    (void)wsum;
+#endif
 }
 #endif
 
@@ -152,7 +168,7 @@ fbnn_offsets(int* __restrict__ cnt, int* __restrict__ hdr, int* __restrict__ per
         perm[p] = -1;
         cneg[p] = NN_PAD_TERM;
     }
-    for (long p = (long)kodd * 16 + mo + tid; p < (long)MT1 * 16; p += 1024) {
+    for (long p = (long)kodd * 16 + mo + tid; p < (long)MTS * 16; p += 1024) {
         perm[p] = -1;
         cneg[p] = NN_PAD_TERM;
     }
@@ -189,30 +205,33 @@ fbnn_scatter(const int* __restrict__ nn, const int* __restrict__ off, const int*
 #define NT FB_NT
 #define WV FB_WV
 #define CH FB_CH
+#define BT FB_BT
 #define TG FB_TG
-#define PF FB_PF
 #define XCDMAP FB_XCDMAP
+#define NTH (WV * 64)
 #define TPW (NT * 16)
 #define TPG (WV * TPW)
 #define TB ((T + TPG - 1) / TPG)
-#define NCHK ((MT1 + CH - 1) / CH)
+#define NCHK ((MTS + CH - 1) / CH)
+#define RS (D + 16)                  // LDS row stride (bytes): 16 bytes of padding
+#define SEGR (D / 16)                // 16-byte segments per row
+#define NSEG (BT * 16 * SEGR)        // segments per batch
+#define LPT ((NSEG + NTH - 1) / NTH) // segments loaded per thread
+#define PASSES (SPLIT ? 1 : 2)
 
-// 16 bytes of a row, centred (XOR 0x80 per byte); zero past the patch end.
-__device__ __forceinline__ i32x4 ld_centred(const unsigned char* p, bool inside)
-{
-    if (!inside) return i32x4{0, 0, 0, 0};
-    const i32x4 v = *(const i32x4*)p;
-    return v ^ (int)0x80808080u;
-}
+static_assert(BT % TG == 0, "tracking groups must tile the LDS batch");
 
 // At least two waves per SIMD caps the kernel at 256 VGPRs, which lets the
 // compiler keep the accumulators in ordinary VGPRs (no accumulator-register
 // copies before the running maximum).
-extern "C" __global__ void __launch_bounds__(WV * 64) __attribute__((amdgpu_waves_per_eu(2)))
+extern "C" __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2)))
 fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict__ nb,
           const int* __restrict__ perm, const int* __restrict__ cneg, const int* __restrict__ hdr,
           unsigned long long* __restrict__ part)
 {
+    __shared__ __attribute__((aligned(16))) unsigned char arow[2][BT * 16 * RS];
+    __shared__ __attribute__((aligned(16))) int cterm[2][BT * 16];
+
     int lin = blockIdx.x;
 #if XCDMAP
     {   // undo the round-robin over the eight XCDs: the target blocks of one
@@ -222,7 +241,8 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
     }
 #endif
     const int tb = lin % TB, chunk = lin / TB;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, grp = lane >> 4;
 
     // Target fragments (B operand, column = target), resident for the chunk.
@@ -234,7 +254,9 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const int k0 = kb * 64 + grp * 16;
-            bf[nt][kb] = ld_centred(tg + (long)t * D + k0, k0 < D);
+            i32x4 v = {0, 0, 0, 0};
+            if (k0 < D) v = *(const i32x4*)(tg + (long)t * D + k0) ^ (int)0x80808080u;
+            bf[nt][kb] = v;
         }
     }
 
@@ -242,21 +264,46 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) best[nt] = 0ull;
 
-    // Tile k of the partitioned order: this lane's A row (a neighbour,
-    // gathered; padding rows read row 0 and lose on their score term) and
-    // the start values of its four accumulator rows.
-    auto load_rows = [&](int pidx, i32x4* a) {
-        const long row = pidx < 0 ? 0 : pidx;
+    // Batch staging: rows of tiles [k, k + BT) (only tiles < kl are read),
+    // global -> registers, then registers -> LDS buffer, centred.
+    i32x4 sreg[LPT];
+    int creg = 0;
+    auto fetch = [&](int k, int kl) {
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            const int k0 = kb * 64 + grp * 16;
-            a[kb] = ld_centred(nb + row * D + k0, k0 < D);
+        for (int i = 0; i < LPT; ++i) {
+            const int e = tid + i * NTH;
+            i32x4 v = {0, 0, 0, 0};
+            if (e < NSEG) {
+                const int r = e / SEGR, q = e % SEGR;
+                const int kt = k + r / 16;
+                if (kt < kl) {
+                    const long pos = (long)kt * 16 + r % 16;
+#if SPLIT
+                    const int pr = perm[pos];
+                    const long row = pr < 0 ? 0 : pr;   // padding rows lose on their score term
+#else
+                    const long row = pos < M ? pos : M - 1;
+#endif
+                    v = *(const i32x4*)(nb + row * D + q * 16);
+                }
+            }
+            sreg[i] = v;
         }
+        if (tid < BT * 16 && k + tid / 16 < kl) creg = cneg[(long)k * 16 + tid];
     };
-    auto perm_at = [&](int k) { return perm[(long)k * 16 + col]; };
-    auto cneg_at = [&](int k) { return *(const i32x4*)(cneg + (long)k * 16 + grp * 4); };
+    auto store = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < LPT; ++i) {
+            const int e = tid + i * NTH;
+            if (e < NSEG) {
+                const int r = e / SEGR, q = e % SEGR;
+                *(i32x4*)&arow[b][r * RS + q * 16] = sreg[i] ^ (int)0x80808080u;
+            }
+        }
+        if (tid < BT * 16) cterm[b][tid] = creg;
+    };
 
-    // Scan tiles [k0, k1) of one parity class (cls 0 even, 1 odd).
+    // Scan tiles [k0, k1) (cls: parity class for SPLIT = 1, else 0).
     auto scan_range = [&](int k0, int k1, int cls) {
         if (k0 >= k1) return;
         int mx[NT], st[NT];
@@ -265,61 +312,68 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
             mx[nt] = -2147483647 - 1;
             st[nt] = k0;
         }
-        i32x4 af[KB], ci = cneg_at(k0);
-        load_rows(perm_at(k0), af);
-        int pn = (k0 + 1 < k1) ? perm_at(k0 + 1) : 0;
+        fetch(k0, k1);
+        store(0);
+        __syncthreads();
+        int buf = 0;
 #pragma unroll 1
-        for (int g0 = k0; g0 < k1; g0 += TG) {
-            int gm[NT];                      // max(running maximum, this group)
+        for (int kb0 = k0; kb0 < k1; kb0 += BT) {
+            const bool more = kb0 + BT < k1;
+            if (more) fetch(kb0 + BT, k1);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) gm[nt] = mx[nt];
+            for (int g = 0; g < BT; g += TG) {
+                if (kb0 + g < k1) {
+                    int gm[NT];              // max(running maximum, this group)
 #pragma unroll
-            for (int j = 0; j < TG; ++j) {
-                const int k = g0 + j;
-                if (k < k1) {
-#if PF
-                    i32x4 an[KB], cn;
-                    int pn2 = 0;
-                    if (k + 1 < k1) {
-                        load_rows(pn, an);
-                        cn = cneg_at(k + 1);
-                        if (k + 2 < k1) pn2 = perm_at(k + 2);
+                    for (int nt = 0; nt < NT; ++nt) gm[nt] = mx[nt];
+#pragma unroll
+                    for (int j = 0; j < TG; ++j) {
+                        const int tl = g + j;
+                        if (kb0 + tl < k1) {
+                            i32x4 af[KB];
+#pragma unroll
+                            for (int kb = 0; kb < KB; ++kb) {
+                                const int k0b = kb * 64 + grp * 16;
+                                i32x4 v = {0, 0, 0, 0};
+                                if (k0b < D) v = *(const i32x4*)&arow[buf][(tl * 16 + col) * RS + k0b];
+                                af[kb] = v;
+                            }
+                            const i32x4 ci = *(const i32x4*)&cterm[buf][tl * 16 + grp * 4];
+#pragma unroll
+                            for (int nt = 0; nt < NT; ++nt) {
+                                i32x4 acc = ci;
+#pragma unroll
+                                for (int pass = 0; pass < PASSES; ++pass)
+#pragma unroll
+                                    for (int kb = 0; kb < KB; ++kb)
+                                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[kb], bf[nt][kb], acc, 0, 0, 0);
+                                gm[nt] = max(max(gm[nt], acc[0]), acc[1]);
+                                gm[nt] = max(max(gm[nt], acc[2]), acc[3]);
+                            }
+                        }
                     }
-#endif
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
-                        i32x4 acc = ci;
-#pragma unroll
-                        for (int kb = 0; kb < KB; ++kb)
-                            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[kb], bf[nt][kb], acc, 0, 0, 0);
-                        gm[nt] = max(max(gm[nt], acc[0]), acc[1]);
-                        gm[nt] = max(max(gm[nt], acc[2]), acc[3]);
-                    }
-                    if (k + 1 < k1) {
-#if PF
-#pragma unroll
-                        for (int kb = 0; kb < KB; ++kb) af[kb] = an[kb];
-                        ci = cn;
-                        pn = pn2;
-#else
-                        load_rows(perm_at(k + 1), af);
-                        ci = cneg_at(k + 1);
-#endif
+                        st[nt] = gm[nt] != mx[nt] ? kb0 + g : st[nt];
+                        mx[nt] = gm[nt];
                     }
                 }
             }
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                st[nt] = gm[nt] != mx[nt] ? g0 : st[nt];
-                mx[nt] = gm[nt];
-            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
         }
         // Key = (exact score S mapped to unsigned order) : (~first row of the
-        // group), so the unsigned maximum takes the higher S, then the
-        // earlier group.
+        // group): the unsigned maximum takes the higher S, then the earlier
+        // group.
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const unsigned hi = (unsigned)(2 * mx[nt] - cls) ^ 0x80000000u;
+#if SPLIT
+            const int S = 2 * mx[nt] - cls;
+#else
+            const int S = mx[nt];
+#endif
+            const unsigned hi = (unsigned)S ^ 0x80000000u;
             const unsigned lo = 0xFFFFFFFFu - (unsigned)st[nt] * 16u;
             const unsigned long long key = ((unsigned long long)hi << 32) | lo;
             best[nt] = key > best[nt] ? key : best[nt];
@@ -327,10 +381,15 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
     };
 
     const int k_begin = chunk * CH;
-    const int k_end = (k_begin + CH < MT1) ? k_begin + CH : MT1;
+    const int k_end = (k_begin + CH < MTS) ? k_begin + CH : MTS;
+#if SPLIT
     const int kodd = hdr[HDR_KODD];
     scan_range(k_begin, min(k_end, kodd), 0);
     scan_range(max(k_begin, kodd), k_end, 1);
+#else
+    (void)hdr;
+    scan_range(k_begin, k_end, 0);
+#endif
 
     // merge the four lane groups of each target and store the chunk's key
 #pragma unroll
@@ -407,8 +466,13 @@ fbnn_final(const unsigned char* __restrict__ tg, const unsigned char* __restrict
         const int tl = e / CAND, j = e % CAND;
         const int tt = blockIdx.x * 64 + tl;
         const long pos = (long)g0s[tl] * 16 + j;
-        if (tt < T && pos < (long)MT1 * 16) {
+        if (tt < T && pos < (long)MTS * 16) {
+#if SPLIT
             const int orig = perm[pos];
+#else
+            const int orig = pos < M ? (int)pos : -1;
+            (void)perm;
+#endif
             if (orig >= 0) {
                 const int d = sq_dist(tg + (long)tt * D, nb + (long)orig * D);
                 atomicMin(&win[tl], ((unsigned long long)(unsigned)d << 32) | (unsigned)orig);

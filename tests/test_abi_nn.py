@@ -28,17 +28,21 @@ def test_header_symbols_exported():
                                    (5, 77, 512), (0, 50, 64)])
 def test_compile_for_gfx950(T, M, D):
     from paper_0911_3456_amd import nn_compile_check
-    assert nn_compile_check(T, M, D) > 1000
+    for split in (0, 1):
+        assert nn_compile_check(T, M, D, "split=%d" % split) > 1000
 
 
 def test_bad_configs_and_descriptors():
     from paper_0911_3456_amd import FbcorrError, nn_compile_check
-    for cfg in ["nt=0", "nt=9", "wv=0", "wv=17", "ch=0", "pf=2", "xcd=3", "fw=0", "bogus", "algo=igemm",
-                "nt=4 mt=2"]:
+    for cfg in ["nt=0", "nt=9", "wv=0", "wv=17", "ch=0", "pf=1", "xcd=3", "fw=0", "bogus", "algo=igemm",
+                "nt=4 mt=2", "bt=3", "bt=2 tg=4", "tg=3", "split=2"]:
         with pytest.raises(FbcorrError):
             nn_compile_check(64, 1000, 64, cfg)
     with pytest.raises(FbcorrError) as e:
         nn_compile_check(64, 1000, 512, "nt=4")      # target fragments over the register budget
+    assert e.value.status_name == "FBCORR_ERR_UNSUPPORTED"
+    with pytest.raises(FbcorrError) as e:
+        nn_compile_check(64, 1000, 512, "nt=1 bt=16")  # LDS batch over the device limit
     assert e.value.status_name == "FBCORR_ERR_UNSUPPORTED"
     for T, M, D in [(1, 1, 15), (1, 1, 0), (1, 1, 528), (1, 0, 64), (-1, 5, 64)]:
         with pytest.raises(FbcorrError) as e:

@@ -17,8 +17,10 @@ pytestmark = pytest.mark.gpu
 
 # Explicit configurations the tests install (validated on the host by
 # tests/test_abi_nn.py before any GPU run).
-NN_CFGS = ["nt=1 wv=1 ch=1 pf=0 tg=1", "nt=2 wv=4 ch=3 pf=1 tg=2", "nt=4 wv=4 ch=64 pf=1 tg=4", "nt=8 wv=2 ch=1000 pf=1",
-           "nt=4 wv=8 ch=7 pf=0 xcd=0", "nt=1 wv=2 ch=2 fw=1", "nt=8 wv=1 ch=16 fw=16"]
+NN_CFGS = ["nt=1 wv=1 ch=1 bt=1 tg=1 split=0", "nt=1 wv=1 ch=1 bt=1 tg=1 split=1",
+           "nt=2 wv=4 ch=3 bt=2 tg=2 split=1", "nt=4 wv=4 ch=64 bt=4 tg=4 split=0",
+           "nt=8 wv=2 ch=1000 bt=8 tg=2 split=1", "nt=4 wv=8 ch=7 bt=16 tg=4 split=1 xcd=0",
+           "nt=1 wv=2 ch=2 bt=4 tg=1 split=0 fw=1", "nt=8 wv=1 ch=16 bt=2 tg=1 split=1 fw=16"]
 
 
 def _dev(a):
@@ -76,7 +78,8 @@ def test_configurations_exact(cfg):
         _assert_exact(t, n, idx, dist, cfg)
 
 
-@pytest.mark.parametrize("cfg", [None, "nt=1 wv=1 ch=1", "nt=4 wv=4 ch=5"])
+@pytest.mark.parametrize("cfg", [None, "nt=1 wv=1 ch=1 split=0", "nt=1 wv=1 ch=1 split=1",
+                                 "nt=4 wv=4 ch=5 bt=4 tg=4 split=1", "nt=4 wv=4 ch=5 bt=4 tg=2 split=0"])
 def test_ties_and_duplicates(cfg):
     """Equal distances must resolve to the lowest index wherever the equal
     rows fall: same tile, same row group, other chunks, other lane groups."""
@@ -184,8 +187,8 @@ def test_timing_and_config_roundtrip():
     with pytest.raises(FbcorrError):
         plan.set_config("nt=99")
     assert plan.get_config() == before
-    plan.set_config("nt=2 ch=4")
-    assert "nt=2" in plan.get_config() and "ch=4" in plan.get_config()
+    plan.set_config("nt=2 ch=4 split=1")
+    assert "nt=2" in plan.get_config() and "ch=4" in plan.get_config() and "split=1" in plan.get_config()
 
 
 def test_parity_classes():
@@ -211,7 +214,7 @@ def test_parity_classes():
         [row((0, 130)), row((1, 130)), row((2, 126))],
         [row((0, 129)), row((1, 131)), row((2, 127))],
     ]
-    for cfg in (None, "tg=2 ch=1", "tg=4 nt=1 wv=1"):
+    for cfg in ("split=0", "split=1", "split=1 tg=2 ch=1", "split=1 bt=4 tg=4 nt=1 wv=1", "split=0 bt=8 tg=4"):
         for n in cases:
             n = np.stack(n * 7)               # repeats: ties to the first copy
             idx, dist, _ = _search(t, n, cfg)
