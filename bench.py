@@ -80,11 +80,21 @@ def kernel_fingerprint(plan, role: str) -> str:
     return hashlib.sha256((src + "\0" + opts).encode()).hexdigest()[:16]
 
 
-def load_traffic(role: str, fingerprint: str):
+NN_TRAFFIC = "traffic_nn_4096x1048576x64.txt"
+FP32_TRAFFIC = "traffic_fp32_256x256x8_64x9x9x8.txt"
+
+
+def nn_fingerprint(plan) -> str:
+    """Hash of the nearest-neighbour kernel template, configuration and shape."""
+    src = open(os.path.join(ROOT, "paper_0911_3456_amd", "csrc", "kernels", "nn.hip")).read()
+    return hashlib.sha256((src + "\0" + plan.get_config() + "\0" + repr(plan.shape)).encode()).hexdigest()[:16]
+
+
+def load_traffic(role: str, fingerprint: str, name: str = FP32_TRAFFIC):
     """HBM bytes per launch (fetch + write) from the committed rocprofv3
     counter summary, if it was taken on exactly this kernel (same generated
     source and options); None otherwise."""
-    path = os.path.join(ROOT, "profiles", "traffic_fp32_256x256x8_64x9x9x8.txt")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -123,6 +133,15 @@ def traffic_probe():
     torch.cuda.synchronize()
     for r in ROLES:
         print(r, kernel_fingerprint(plan, r), plan.get_config(r), flush=True)
+    from paper_0911_3456_amd import NNPlan
+    T, M, D = wl.NN_TARGETS, wl.NN_NEIGHBOURS[-1], wl.NN_PATCH * wl.NN_PATCH
+    t, n = wl.draw_nn(T, M, seed=7)
+    tt, nt = torch.from_numpy(t).to(dev), torch.from_numpy(n).to(dev)
+    nplan = NNPlan(T, M, D, device=dev)
+    for _ in range(3):
+        nplan.search(tt, nt)
+    torch.cuda.synchronize()
+    print("nn_scan", nn_fingerprint(nplan), nplan.get_config(), flush=True)
 
 
 def time_steps(fn, steps: int, warmup: int):
@@ -294,6 +313,7 @@ def nn_leg(steps: int, warmup: int):
                    PAPER_NN_GTX295_S[m] / sec, 1), "config": plan.get_config()}
         rows.append(row)
         log("nn", m, row["ms"], "ms", row["scan_tops"], "TOP/s scan")
+        big_fp = nn_fingerprint(plan)
         plan.close()
     big = rows[-1]
     achieved = big["scan_tops"]
@@ -302,7 +322,8 @@ def nn_leg(steps: int, warmup: int):
             "rows": rows,
             "roofline": {"bound": "mfma", "kernel": "fbnn_scan", "achieved": achieved,
                          "peak": INT8_MATRIX_PEAK_TOPS, "unit": "TOP/s",
-                         "frac": round(achieved / INT8_MATRIX_PEAK_TOPS, 4), "traffic": None}}
+                         "frac": round(achieved / INT8_MATRIX_PEAK_TOPS, 4),
+                         "traffic": load_traffic("nn_scan", big_fp, NN_TRAFFIC), "fingerprint": big_fp}}
 
 
 def paper_table(reps: int):
