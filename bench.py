@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="skip the extra timing of the step with dW overlapped on a side stream")
     ap.add_argument("--paper-table", action="store_true",
                     help="default vs auto-tuned forward on the paper's four table shapes, then exit")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -487,7 +489,7 @@ def main():
                    "kernels": {r: plan.get_config(r) for r in ROLES}},
         "roofline": roofline,
     }
-    if args.only == "step":
+    if args.only == "step" and not args.no_overlap:
         # the same step with dW overlapped on a side stream (FBCORR_FLAG_OVERLAP_BACKWARD)
         po = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, device=dev, overlap_backward=True)
         for r in ROLES:

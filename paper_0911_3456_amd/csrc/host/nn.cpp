@@ -136,7 +136,10 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     if (g.nt < 1 || g.nt > 8) { err = "nt must be in [1, 8]"; return false; }
     if (g.nt * kb > 16) { err = "nt * ceil(dim/64) > 16 (target fragments would not fit in registers)"; return false; }
     if (g.wv < 1 || g.wv * 64 > di.max_threads) { err = "wv out of range"; return false; }
-    if (g.fw < 1 || g.fw > 16) { err = "fw must be in [1, 16]"; return false; }
+    if (g.fw != 1 && g.fw != 2 && g.fw != 4 && g.fw != 8 && g.fw != 16) {
+        err = "fw must be 1, 2, 4, 8 or 16";
+        return false;
+    }
     if (g.ch < 1) { err = "ch must be >= 1"; return false; }
     if (g.bt != 1 && g.bt != 2 && g.bt != 4 && g.bt != 8 && g.bt != 16) { err = "bt must be 1, 2, 4, 8 or 16"; return false; }
     if (g.tg != 1 && g.tg != 2 && g.tg != 4) { err = "tg must be 1, 2 or 4"; return false; }
@@ -156,7 +159,7 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     g.offsets = LaunchGeom{1, 1, 1024, 0};
     g.scatter = LaunchGeom{(int)g.nblk, 1, 64, 0};
     g.scan = LaunchGeom{(int)(g.tb * g.nchk), 1, g.wv * 64, 0};
-    g.fin = LaunchGeom{(int)std::max(1L, cdiv(T, 64)), 1, g.fw * 64, 0};
+    g.fin = LaunchGeom{(int)std::max(1L, cdiv(T, 16)), 1, g.fw * 64, 0};
     size_t off = 0;
     g.off_hdr = off;  off += 256;
     if (g.split) {

@@ -56,7 +56,7 @@
 //   scan     NT (16-target tiles per wave)  WV (waves per workgroup)
 //            CH (tiles per chunk)  BT (tiles per LDS batch)
 //            TG (tiles per tracking group, divides BT)  XCDMAP
-//   final    FW (waves per workgroup)  TG  NCHK (chunks)
+//   final    FW (waves per workgroup, 1, 2, 4, 8 or 16)  TG  NCHK (chunks)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -433,39 +433,47 @@ __device__ __forceinline__ int sq_dist(const unsigned char* a, const unsigned ch
     return s;
 }
 
-// 64 targets per workgroup: first one per lane (the FW waves split the
-// chunks), then the workgroup's threads re-measure the 64 x CAND candidates.
+// 16 targets per workgroup.  Thread (target tl = tid % 16, chunk lane
+// cl = tid / 16) takes chunks cl, cl + CL, ... (16 consecutive targets of
+// one chunk are one 128-byte row of part), the CL chunk lanes are merged
+// in LDS, then the workgroup's threads re-measure the 16 x CAND candidates.
+#define FT 16
+#define CL (FW * 64 / FT)
 extern "C" __global__ void __launch_bounds__(FW * 64)
 fbnn_final(const unsigned char* __restrict__ tg, const unsigned char* __restrict__ nb,
            const int* __restrict__ perm, const unsigned long long* __restrict__ part,
            int* __restrict__ idx, int* __restrict__ dist)
 {
-    __shared__ unsigned long long red[FW][64];
-    __shared__ unsigned long long win[64];
-    __shared__ int g0s[64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int t = blockIdx.x * 64 + lane;
+    __shared__ unsigned long long red[CL][FT];
+    __shared__ unsigned long long win[FT];
+    __shared__ int g0s[FT];
+    const int tid = threadIdx.x;
+    const int tl = tid % FT, cl = tid / FT;
+    const int t = blockIdx.x * FT + tl;
     unsigned long long key = 0;
     if (t < T) {
-#pragma unroll 8
-        for (int c = wave; c < NCHK; c += FW) {
+#pragma unroll 4
+        for (int c = cl; c < NCHK; c += CL) {
             const unsigned long long v = part[(long)c * T + t];
             key = v > key ? v : key;
         }
     }
-    red[wave][lane] = key;
-    if (wave == 0) win[lane] = ~0ull;
+    red[cl][tl] = key;
+    if (tid < FT) win[tid] = ~0ull;
     __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int w = 1; w < FW; ++w) key = red[w][lane] > key ? red[w][lane] : key;
-        g0s[lane] = (int)((0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull)) >> 4);
+    for (int h = CL / 2; h > 0; h >>= 1) {          // CL is a power of two
+        if (cl < h) {
+            const unsigned long long o = red[cl + h][tl];
+            if (o > red[cl][tl]) red[cl][tl] = o;
+        }
+        __syncthreads();
     }
+    if (tid < FT) g0s[tid] = (int)((0xFFFFFFFFu - (unsigned)(red[0][tid] & 0xFFFFFFFFull)) >> 4);
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * CAND; e += FW * 64) {
-        const int tl = e / CAND, j = e % CAND;
-        const int tt = blockIdx.x * 64 + tl;
-        const long pos = (long)g0s[tl] * 16 + j;
+    for (int e = tid; e < FT * CAND; e += FW * 64) {
+        const int el = e / CAND, j = e % CAND;
+        const int tt = blockIdx.x * FT + el;
+        const long pos = (long)g0s[el] * 16 + j;
         if (tt < T && pos < (long)MTS * 16) {
 #if SPLIT
             const int orig = perm[pos];
@@ -475,14 +483,14 @@ fbnn_final(const unsigned char* __restrict__ tg, const unsigned char* __restrict
 #endif
             if (orig >= 0) {
                 const int d = sq_dist(tg + (long)tt * D, nb + (long)orig * D);
-                atomicMin(&win[tl], ((unsigned long long)(unsigned)d << 32) | (unsigned)orig);
+                atomicMin(&win[el], ((unsigned long long)(unsigned)d << 32) | (unsigned)orig);
             }
         }
     }
     __syncthreads();
-    if (wave == 0 && t < T) {
-        idx[t] = (int)(unsigned)(win[lane] & 0xFFFFFFFFull);
-        dist[t] = (int)(unsigned)(win[lane] >> 32);
+    if (tid < FT && blockIdx.x * FT + tid < T) {
+        idx[blockIdx.x * FT + tid] = (int)(unsigned)(win[tid] & 0xFFFFFFFFull);
+        dist[blockIdx.x * FT + tid] = (int)(unsigned)(win[tid] >> 32);
     }
 }
 #endif
