@@ -83,7 +83,9 @@ static std::string cache_key(const KernelSource& ks, const std::string& arch) {
     char buf[40];
     snprintf(buf, sizeof buf, "%016llx-%016llx", (unsigned long long)fnv1a(all),
              (unsigned long long)fnv1a(all, 0x84222325cbf29ce4ull));
-    return ks.name + "-" + buf;
+    // Named after the template, not the kernel: every kernel of one code
+    // object (e.g. a dispatch kernel and its reset kernel) shares the entry.
+    return ks.file + "-" + buf;
 }
 
 // Semi-permanent on-disk cache (Fig. 2: compiled code survives the process
@@ -145,6 +147,16 @@ static bool supported_arch(const std::string& a) {
     return a == "gfx950";
 }
 
+// FBCORR_CACHE_TRACE=1 prints one line per lookup to stderr: where the code
+// object came from (memory, disk, compile) and its key.
+static void trace_lookup(const char* where, const std::string& key) {
+    static const bool on = [] {
+        const char* e = getenv("FBCORR_CACHE_TRACE");
+        return e && *e && strcmp(e, "0") != 0;
+    }();
+    if (on) fprintf(stderr, "fbcorr cache: %-7s %s\n", where, key.c_str());
+}
+
 fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
                              std::shared_ptr<const std::vector<char>>& code) {
     FBC_RETURN_IF(!supported_arch(arch), FBCORR_ERR_UNSUPPORTED, "architecture '" + arch + "' is not supported");
@@ -152,7 +164,12 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_code.find(key);
-        if (it != g_code.end()) { ++g_hits; code = it->second; return FBCORR_OK; }
+        if (it != g_code.end()) {
+            ++g_hits;
+            code = it->second;
+            trace_lookup("memory", key);
+            return FBCORR_OK;
+        }
     }
     {
         auto buf = std::make_shared<std::vector<char>>();
@@ -161,6 +178,7 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
             ++g_disk_hits;
             g_code[key] = buf;
             code = buf;
+            trace_lookup("disk", key);
             return FBCORR_OK;
         }
     }
@@ -168,6 +186,7 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
         std::lock_guard<std::mutex> lk(g_cache_mu);
         ++g_misses;
     }
+    trace_lookup("compile", key);
     hiprtcProgram prog;
     hiprtcResult r = hiprtcCreateProgram(&prog, ks.source.c_str(), (ks.file + ".hip").c_str(), 0, nullptr, nullptr);
     FBC_RETURN_IF(r != HIPRTC_SUCCESS, FBCORR_ERR_COMPILE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));

@@ -209,6 +209,22 @@ def test_disk_cache_reuse_and_corruption(tmp_path, monkeypatch):
     assert cache_stats()["disk_hits"] == s5["disk_hits"]
 
 
+def test_cache_entry_shared_by_kernels_of_one_code_object(tmp_path, monkeypatch):
+    """The cache key names the template, not the kernel: the persistent
+    batched kernel and its counter-reset kernel (one generated source) share
+    one on-disk entry, so a plan never recompiles the module for the second
+    kernel."""
+    import workloads as wl
+    from paper_0911_3456_amd import _native as nat
+    monkeypatch.setenv("FBCORR_CACHE_DIR", str(tmp_path))
+    nat.cache_clear()
+    shapes, _ = wl.draw_batched_list(count=6, seed=31)
+    nat.compile_check_batched([nat.make_desc(1, s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes])
+    names = [f.name for f in tmp_path.glob("*.co")]
+    assert len(names) == 1 and names[0].startswith("batched-"), names
+    nat.cache_clear()
+
+
 def test_tuning_database_supplies_defaults(tmp_path, monkeypatch):
     from paper_0911_3456_amd import cache_clear, codegen, make_desc
     db = tmp_path / "db.txt"
