@@ -139,7 +139,7 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         std::vector<Config> grid;
         for (int rh : {1, 2, 4})
             for (int rw : {32, 64})
-                for (int nw : {2, 4, 8})
+                for (int nw : {2, 4, 6, 8, 12, 14, 16})
                     for (int split : {1, 2, 3, 4, 6})
                         for (int np : {32, 64, 128, 256})
                             for (int pf : {0, 1}) {
