@@ -422,12 +422,15 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
         if (!geom_dw(c, d, di, rb.main_geom, rb.main, np, err)) return false;
         rb.np = np;
         const long L = (long)d.N * K;
-        const int rs = 8;
+        // 16 slices x 16 lanes per workgroup: several hundred workgroups for
+        // a few hundred kilobytes of output, each thread with NP/16 loads
+        const int rs = 16, lanes = 16;
         const int sv = (L % 4 == 0) ? 4 : 1;    // outputs per thread (16-byte loads when possible)
         KernelSource ks = util_source("fbcorr_sum_partials", "SUM_PARTIALS");
         opt(ks.options, "L", L); opt(ks.options, "NP", np); opt(ks.options, "RS", rs);
+        opt(ks.options, "LANES", lanes);
         rb.aux.push_back(ks);
-        rb.aux_geom.push_back(LaunchGeom{cdivl(L / sv, 64), 1, 64 * rs, 0});
+        rb.aux_geom.push_back(LaunchGeom{cdivl(L / sv, lanes), 1, lanes * rs, 0});
         rb.ws_bytes = align256((size_t)np * L * 4);
         return true;
     }

@@ -4,7 +4,8 @@
 //                        p = k, k+RS, k+2RS, ... in increasing order, then the
 //                        RS slice sums are added in increasing k (a fixed
 //                        order, so the result is deterministic); four
-//                        consecutive i per thread when L % 4 == 0.
+//                        consecutive i per thread when L % 4 == 0, LANES
+//                        threads per slice.
 //   fbcorr_flip_filters  wf[d,u,v,n] = w[n, FH-1-u, FW-1-v, d]: the filters of
 //                        the input-gradient correlation.
 //   fbcorr_pack_lowp     per filter n: e_n = floor(log2 max|w[n]|),
@@ -13,7 +14,7 @@
 //                        (an all-zero filter gets e_n = 0).
 //   fbcorr_fill_int      integer-valued pattern in [-R, R] (tuner gate data).
 //
-// Compile-time constants: L NP RS (sum); N FH FW D (flip, pack); LOWP (pack).
+// Compile-time constants: L NP RS LANES (sum); N FH FW D (flip, pack); LOWP (pack).
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -45,16 +46,22 @@
 #endif
 
 #ifdef FB_SUM_PARTIALS
-// Four consecutive outputs per thread when L allows 16-byte loads.
+// Four consecutive outputs per thread when L allows 16-byte loads; a
+// workgroup covers LANES x SV outputs with RS slices.
 #define SV ((L % 4 == 0) ? 4 : 1)
 #define LV (L / SV)
+#ifdef FB_LANES
+#define LANES FB_LANES
+#else
+#define LANES 64
+#endif
 typedef float f32x4s __attribute__((ext_vector_type(4)));
-extern "C" __global__ void __launch_bounds__(64 * RS)
+extern "C" __global__ void __launch_bounds__(LANES * RS)
 fbcorr_sum_partials(const float* __restrict__ part, float* __restrict__ out)
 {
-    __shared__ float red[RS][64 * SV];
-    const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const long i = (long)blockIdx.x * 64 + e;        // in units of SV floats
+    __shared__ float red[RS][LANES * SV];
+    const int e = threadIdx.x % LANES, sl = threadIdx.x / LANES;
+    const long i = (long)blockIdx.x * LANES + e;     // in units of SV floats
 #if SV == 4
     f32x4s acc = {0.f, 0.f, 0.f, 0.f};
     if (i < LV) {
