@@ -5,7 +5,11 @@ the input gradient and the filter gradient, in fp32, on the 256x256x8 input
 with 64 filters 9x9x8 (the first shape of the paper's table "Performance of
 RTCG auto-tuning on 3D filter-bank convolutions").  Inputs are seeded
 synthetic data resident in GPU memory before timing starts.  value =
-3 * 2 * multiply-adds of one forward pass / seconds per step.
+3 * 2 * multiply-adds of one forward pass / seconds per step, the step's
+launches captured once into a HIP graph and replayed (--no-graph: eager
+launches; the eager time is reported beside it).  Per-kernel times for the
+roofline come from HIP events around each kernel in the eager pass (the
+kernels are the same in both).
 
 Also printed in the same JSON line:
   roofline      the dominant kernel's algorithmic flops per launch over its
@@ -59,6 +63,8 @@ def parse():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the step as eager launches instead of replaying a captured HIP graph")
     ap.add_argument("--no-overlap", action="store_true",
                     help="skip the extra timing of the step with dW overlapped on a side stream")
     ap.add_argument("--paper-table", action="store_true",
@@ -452,10 +458,26 @@ def main():
     torch.cuda.synchronize()
     plan.read_timing(reset=True)
     plan.enable_timing(True)
-    sec = time_steps(fn, args.steps, 0)
+    sec_eager = time_steps(fn, args.steps, 0)
     plan.enable_timing(False)
     timing = plan.read_timing(reset=True)
     flops_step = 3 * s.flops if args.only == "step" else s.flops
+    sec = sec_eager
+    graph_used = False
+    if args.only == "step" and not args.no_graph:
+        # The step's launches captured once into a HIP graph and replayed: the
+        # same kernels without the gaps between eager launches.
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fn()
+        sec = time_steps(graph.replay, args.steps, args.warmup)
+        graph_used = True
     value = flops_step / sec / 1e9
 
     kern = {r: timing[r][0] / timing[r][1] for r in ROLES if timing[r][1] > 0}
@@ -478,6 +500,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(sec * 1e3, 5),
+        "eager_ms_per_step": round(sec_eager * 1e3, 5),
+        "graph": graph_used,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -498,7 +522,19 @@ def main():
         def step_overlapped():
             po.forward(xt, wt, y)
             po.backward(xt, wt, gt, dx=dx, dw=dw)
-        so = time_steps(step_overlapped, args.steps, args.warmup)
+        run_o = step_overlapped
+        if not args.no_graph:
+            side = torch.cuda.Stream(device=dev)
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                step_overlapped()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph_o = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph_o):
+                step_overlapped()
+            run_o = graph_o.replay
+        so = time_steps(run_o, args.steps, args.warmup)
         result["overlapped_backward"] = {"ms_per_step": round(so * 1e3, 5),
                                          "gflops": round(flops_step / so / 1e9, 3)}
         po.close()
