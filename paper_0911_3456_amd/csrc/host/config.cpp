@@ -305,7 +305,9 @@ static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di,
     const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
     const int npad = cdiv(d.N, 32) * 32;
     const int pc = rh * rw;
-    const long lds = ((long)pc * (npad + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
+    if (pf < 0 || pf > 2) { err = "dw: pf must be 0, 1 or 2"; return false; }
+    const long lds = (pf == 2 ? 2 : 1) *
+                     ((long)pc * (npad + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
     if (lds > di.lds_per_block) { err = "dw: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
     const long prefetch_regs = pf ? (cdivl((long)pc * npad, threads) + cdivl((long)(rh + d.fh - 1) * (rw + d.fw - 1) * d.D, threads)) : 0;
     if (prefetch_regs > 96) { err = "dw: prefetch needs too many registers"; return false; }
@@ -326,7 +328,7 @@ static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di,
     opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
     opt(ks.options, "RH", rh); opt(ks.options, "RW", rw); opt(ks.options, "NW", nw); opt(ks.options, "TPB", tpb_eff);
     opt(ks.options, "NP", np); opt(ks.options, "GPAD", gpad); opt(ks.options, "XPAD", xpad);
-    opt(ks.options, "PF", pf ? 1 : 0);
+    opt(ks.options, "PF", pf);
     return true;
 }
 

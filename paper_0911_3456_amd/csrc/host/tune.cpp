@@ -142,7 +142,7 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                 for (int nw : {2, 4, 6, 8, 12, 14, 16})
                     for (int split : {1, 2, 3, 4, 6})
                         for (int np : {32, 64, 128, 256})
-                            for (int pf : {0, 1}) {
+                            for (int pf : {0, 1, 2}) {
                                 Config c = base;
                                 c.v["rh"] = rh; c.v["rw"] = rw; c.v["nw"] = nw;
                                 c.v["tpb"] = (tiles + split - 1) / split;

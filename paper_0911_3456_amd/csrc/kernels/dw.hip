@@ -13,14 +13,17 @@
 // Per chunk, dy[chunk][all n] and the matching input tile with its
 // (FH-1, FW-1) halo are staged in LDS; with PF the next chunk is fetched into
 // registers while the current one is consumed (pre-fetching and software
-// pipelining).  The B fragment of a lane for tap column q is the input value
+// pipelining); with PF = 2 the LDS copy is double-buffered as well, so the
+// next chunk is written to LDS while other waves still compute and each
+// chunk costs one barrier.  The B fragment of a lane for tap column q is the input value
 // at its pixel offset by (u, v), channel d.
 //
 // Compile-time constants (FB_<name>):
 //   problem  BATCH FH FW D N H W HO WO
 //   tiling   RH RW (pixel chunk)  NW (waves)  TPB (tiles per workgroup)
 //            NP (partials = workgroup columns)  GPAD XPAD (LDS padding)
-//            PF (register prefetch of the next chunk)
+//            PF (0: none, 1: register prefetch of the next chunk,
+//                2: register prefetch + double-buffered LDS)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -77,12 +80,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 static_assert(PC % 2 == 0, "pixel chunk must be even");
 
+#define NBUF (PF == 2 ? 2 : 1)
+
 extern "C" __global__ void __launch_bounds__(NTHREADS)
 fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
                   float* __restrict__ part)
 {
-    __shared__ __attribute__((aligned(16))) float gl[PC * GST];
-    __shared__ __attribute__((aligned(16))) float xl[XR * XRS];
+    __shared__ __attribute__((aligned(16))) float gl_all[NBUF][PC * GST];
+    __shared__ __attribute__((aligned(16))) float xl_all[NBUF][XR * XRS];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -146,7 +151,9 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
             xreg[r] = v;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int b) {
+        float* gl = gl_all[b];
+        float* xl = xl_all[b];
 #pragma unroll
         for (int r = 0; r < GPER; ++r) {
             const int e = tid + r * NTHREADS;
@@ -159,15 +166,10 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
         }
     };
 
-    if (g < NCHUNKS) fetch(g);
-#pragma unroll 1
-    for (int ch = g; ch < NCHUNKS; ch += NP) {
-        __syncthreads();               // everyone is done with the previous chunk
-        store();
-        __syncthreads();
-#if PF
-        if (ch + NP < NCHUNKS) fetch(ch + NP);    // in flight during the compute
-#endif
+    // The products of one staged chunk (LDS buffer b).
+    auto compute = [&](int b) {
+        const float* gl = gl_all[b];
+        const float* xl = xl_all[b];
         // Lane half h walks pixels [h*PC/2, (h+1)*PC/2) of the chunk.
 #pragma unroll 4
         for (int t = 0; t < PC / 2; ++t) {
@@ -187,10 +189,45 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
                 acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
             }
         }
+    };
+
+#if PF == 2
+    // Double-buffered: chunk ch is in LDS buffer b, chunk ch + NP in
+    // registers; after computing ch the registers go to the other buffer and
+    // ch + 2NP is fetched.  One barrier per chunk.
+    if (g < NCHUNKS) {
+        fetch(g);
+        store(0);
+        if (g + NP < NCHUNKS) fetch(g + NP);
+    }
+    __syncthreads();
+    int buf = 0;
+#pragma unroll 1
+    for (int ch = g; ch < NCHUNKS; ch += NP) {
+        compute(buf);
+        if (ch + NP < NCHUNKS) {
+            store(buf ^ 1);
+            if (ch + 2 * NP < NCHUNKS) fetch(ch + 2 * NP);
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+#else
+    if (g < NCHUNKS) fetch(g);
+#pragma unroll 1
+    for (int ch = g; ch < NCHUNKS; ch += NP) {
+        __syncthreads();               // everyone is done with the previous chunk
+        store(0);
+        __syncthreads();
+#if PF
+        if (ch + NP < NCHUNKS) fetch(ch + NP);    // in flight during the compute
+#endif
+        compute(0);
 #if !PF
         if (ch + NP < NCHUNKS) fetch(ch + NP);
 #endif
     }
+#endif
 
     // Partial sums: part[g][n][q] (zeros from workgroups without chunks).
     float* out = part + (long)g * N * QTOT;

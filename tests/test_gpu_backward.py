@@ -86,7 +86,9 @@ BX_CFGS = ["mf=16 kc=4 s=2 mr=4 mt=2 nt=1 wm=2 wn=1 ks=4", "mf=16 kc=8 s=1 mr=2 
            "kc=8 s=2 mr=4 mt=1 nt=1 wm=2 wn=1 ks=3", "kc=8 s=4 mt=1 nt=1 wm=4 wn=1", "kc=8 s=2 mr=1 ks=1 mt=2 nt=1 wm=2 wn=1 ustage=3",
            "kc=4 s=8 mt=1 nt=1 wm=2 wn=1 xcd=0", "kc=8 s=1 mt=1 nt=1 wm=4 wn=1"]
 BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=0",
-           "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=1", "rh=2 rw=32 nw=8 tpb=14 np=300 pf=1"]
+           "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=1", "rh=2 rw=32 nw=8 tpb=14 np=300 pf=1",
+           "rh=2 rw=32 nw=8 tpb=21 np=64 pf=2", "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=2",
+           "rh=4 rw=16 nw=14 tpb=42 np=7 pf=2"]
 
 
 @pytest.mark.parametrize("cfg", BX_CFGS)
