@@ -180,7 +180,9 @@ FBCORR_API fbcorr_status fbcorr_backward(fbcorr_plan_t plan, const float* x, con
  * generates itself, times the survivors with HIP events on `stream`
  * (synchronising it), and installs the fastest.  Uses the caller's buffers:
  * for the forward role x, w, y (y is overwritten); for the backward roles
- * x, w, y (as dy) and ws.  Their contents are preserved except y. */
+ * x, w, y (as dy) and ws.  Their contents are preserved except y.  With the
+ * environment variable FBCORR_TUNE_PROGRESS=1 the tuner prints a progress
+ * line to stderr every 25 candidates compiled and timed. */
 FBCORR_API fbcorr_status fbcorr_tune(fbcorr_plan_t plan, const float* x, const float* w, float* y,
                           void* workspace, size_t workspace_bytes, void* stream,
                           const fbcorr_tune_opts* opts, fbcorr_tune_report* report);

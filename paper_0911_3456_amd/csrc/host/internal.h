@@ -86,6 +86,11 @@ void cache_stats(int64_t& hits, int64_t& misses, int64_t& entries, int64_t& disk
 void cache_clear_memory();
 std::string disk_cache_dir();
 
+// FBCORR_TUNE_PROGRESS=1: the tuners print a progress line to stderr as
+// candidates compile and are timed (long sweeps otherwise run silently).
+bool tune_progress_on();
+void tune_progress(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
 // Device facts used for validation and launch shapes.
 struct DeviceInfo {
     std::string arch;       // e.g. "gfx950"

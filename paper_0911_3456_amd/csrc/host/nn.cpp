@@ -609,6 +609,7 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
     {
         std::vector<fbcorr_status> res(builds.size(), FBCORR_OK);
         std::atomic<size_t> next{0};
+        std::atomic<size_t> done{0};
         auto worker = [&]() {
             for (size_t i; (i = next.fetch_add(1)) < builds.size();) {
                 std::shared_ptr<const std::vector<char>> code;
@@ -617,6 +618,9 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
                     res[i] = compile_cached(ks, p->dev.arch, code);
                     if (res[i] != FBCORR_OK) break;
                 }
+                const size_t n = ++done;
+                if (n % 25 == 0 || n == builds.size())
+                    tune_progress("nearest: compiled %zu of %zu candidates", n, builds.size());
             }
         };
         const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -655,6 +659,7 @@ fbcorr_status fbnn_tune(fbnn_plan_t plan, const uint8_t* targets, const uint8_t*
             best = ms;
             win = b;
         }
+        tune_progress("nearest: timed %d, best %.4f ms (default %.4f ms)", rep.n_compiled, best, dms);
     }
     rep.best_ms = best;
     snprintf(rep.best_cfg, sizeof rep.best_cfg, "%s", win.cfg.str().c_str());

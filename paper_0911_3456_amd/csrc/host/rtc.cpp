@@ -12,6 +12,7 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <cstdarg>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
@@ -145,6 +146,27 @@ static void disk_store(const std::string& key, const std::vector<char>& code) {
 static bool supported_arch(const std::string& a) {
     // The kernels use CDNA3/CDNA4 matrix instructions; gfx950 is the target.
     return a == "gfx950";
+}
+
+bool tune_progress_on() {
+    static const bool on = [] {
+        const char* e = getenv("FBCORR_TUNE_PROGRESS");
+        return e && *e && strcmp(e, "0") != 0;
+    }();
+    return on;
+}
+
+void tune_progress(const char* fmt, ...) {
+    if (!tune_progress_on()) return;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    va_list ap;
+    va_start(ap, fmt);
+    fputs("fbcorr tune: ", stderr);
+    vfprintf(stderr, fmt, ap);
+    fputc('\n', stderr);
+    fflush(stderr);
+    va_end(ap);
 }
 
 // FBCORR_CACHE_TRACE=1 prints one line per lookup to stderr: where the code

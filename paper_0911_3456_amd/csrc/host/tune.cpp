@@ -337,6 +337,7 @@ fbcorr_status tune_plan(Plan* p, const float* x, const float* w, float* y, void*
             std::atomic<size_t> next{0};
             unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
             std::vector<std::thread> pool;
+            std::atomic<size_t> done{0};
             for (unsigned i = 0; i < nth; ++i)
                 pool.emplace_back([&] {
                     for (size_t j; (j = next++) < builds.size();) {
@@ -345,6 +346,9 @@ fbcorr_status tune_plan(Plan* p, const float* x, const float* w, float* y, void*
                         for (auto& a : builds[j].aux)
                             good = good && compile_cached(a, p->dev.arch, code) == FBCORR_OK;
                         ok[j] = good ? 1 : 0;
+                        const size_t n = ++done;
+                        if (n % 25 == 0 || n == builds.size())
+                            tune_progress("role %d: compiled %zu of %zu candidates", role, n, builds.size());
                     }
                 });
             for (auto& th : pool) th.join();
@@ -376,6 +380,9 @@ fbcorr_status tune_plan(Plan* p, const float* x, const float* w, float* y, void*
             double ms = 0;
             if (time_role(p, role, ex, t2, s, warmup, reps, ms) != FBCORR_OK) { rep.n_failed++; continue; }
             if (ms < best) { best = ms; best_i = (int)j; }
+            if ((j + 1) % 25 == 0 || j + 1 == builds.size())
+                tune_progress("role %d: timed %zu of %zu, best %.4f ms (default %.4f ms)", role, j + 1,
+                              builds.size(), best, dms);
         }
         const Config& chosen = best_i >= 0 ? builds[best_i].cfg : dcfg;
         rep.best_ms = best;
