@@ -320,19 +320,6 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
         for (int kb0 = k0; kb0 < k1; kb0 += BT) {
             const bool more = kb0 + BT < k1;
             if (more) fetch(kb0 + BT, k1);
-            // LDS fragments of tile tl of the current batch.
-            auto lds_tile = [&](int tl, i32x4* a, i32x4& c) {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb) {
-                    const int k0b = kb * 64 + grp * 16;
-                    i32x4 v = {0, 0, 0, 0};
-                    if (k0b < D) v = *(const i32x4*)&arow[buf][(tl * 16 + col) * RS + k0b];
-                    a[kb] = v;
-                }
-                c = *(const i32x4*)&cterm[buf][tl * 16 + grp * 4];
-            };
-            i32x4 an[KB], cn;                // next tile's fragments, read one tile ahead
-            lds_tile(0, an, cn);
 #pragma unroll
             for (int g = 0; g < BT; g += TG) {
                 if (kb0 + g < k1) {
@@ -345,25 +332,23 @@ fbnn_scan(const unsigned char* __restrict__ tg, const unsigned char* __restrict_
                         if (kb0 + tl < k1) {
                             i32x4 af[KB];
 #pragma unroll
-                            for (int kb = 0; kb < KB; ++kb) af[kb] = an[kb];
-                            const i32x4 ci = cn;
-                            if (tl + 1 < BT) lds_tile(tl + 1, an, cn);
-                            // all products first (separate accumulators), then the maxima
-                            i32x4 acc[NT];
+                            for (int kb = 0; kb < KB; ++kb) {
+                                const int k0b = kb * 64 + grp * 16;
+                                i32x4 v = {0, 0, 0, 0};
+                                if (k0b < D) v = *(const i32x4*)&arow[buf][(tl * 16 + col) * RS + k0b];
+                                af[kb] = v;
+                            }
+                            const i32x4 ci = *(const i32x4*)&cterm[buf][tl * 16 + grp * 4];
 #pragma unroll
                             for (int nt = 0; nt < NT; ++nt) {
-                                acc[nt] = ci;
+                                i32x4 acc = ci;
 #pragma unroll
                                 for (int pass = 0; pass < PASSES; ++pass)
 #pragma unroll
                                     for (int kb = 0; kb < KB; ++kb)
-                                        acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[kb], bf[nt][kb], acc[nt],
-                                                                                        0, 0, 0);
-                            }
-#pragma unroll
-                            for (int nt = 0; nt < NT; ++nt) {
-                                gm[nt] = max(max(gm[nt], acc[nt][0]), acc[nt][1]);
-                                gm[nt] = max(max(gm[nt], acc[nt][2]), acc[nt][3]);
+                                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[kb], bf[nt][kb], acc, 0, 0, 0);
+                                gm[nt] = max(max(gm[nt], acc[0]), acc[1]);
+                                gm[nt] = max(max(gm[nt], acc[2]), acc[3]);
                             }
                         }
                     }
