@@ -18,6 +18,8 @@ Also printed in the same JSON line:
                 rocprofv3 counter summaries when they match the current
                 kernel source.
   cpu_baseline  the FP64 oracle timed on this host's cores (rank 0 only).
+  direct_fp32   the plain fp32 direct kernel (vector ALU, auto-tuned) on the
+                step's forward pass, against the 78.6 TFLOP/s vector peak.
   precision     the 512x512x16 / 128x13x13x16 forward: fp32 direct,
                 fp32 matrix-core, bf16 and fp16 matrix-core times and the
                 bf16/fp16 speedups (error bounds are enforced by the tests).
@@ -181,6 +183,26 @@ def cpu_baseline(shape, x, w, g, budget_s: float = 20.0):
             "kind": "oracle",
             "sample": "full workload (forward + dX + dW, FP64 C loops, OpenMP), %d repetition(s), %.1f s"
                       % (reps, t_total)}
+
+
+def direct_leg(steps: int, warmup: int, xt, wt, s):
+    """The plain fp32 direct kernel (vector ALU, auto-tuned configuration
+    from the database) on the benchmark workload's forward pass."""
+    import torch
+    from paper_0911_3456_amd import Plan
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, algo="direct", device=xt.device)
+    y = torch.empty(plan.y_shape, device=xt.device)
+    plan.enable_timing(True)
+    t = time_steps(lambda: plan.forward(xt, wt, y), max(5, steps // 2), warmup)
+    ms, calls = plan.read_timing()["forward"]
+    k_ms = ms / max(calls, 1)
+    tf = s.flops / k_ms / 1e9
+    cfg = plan.get_config("forward")
+    plan.close()
+    return {"workload": "forward of the step's workload on the vector-ALU direct kernel",
+            "ms": round(t * 1e3, 4), "kernel_ms": round(k_ms, 4), "tflops": round(tf, 2),
+            "peak_tflops": FP32_VALU_PEAK_TFLOPS, "frac_of_valu_peak": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
+            "config": cfg}
 
 
 def precision_leg(steps: int, warmup: int):
@@ -540,6 +562,9 @@ def main():
         po.close()
     if tune_reports:
         result["tune"] = tune_reports
+    if not args.no_precision and args.only == "step":
+        log("direct fp32 kernel ...")
+        result["direct_fp32"] = direct_leg(args.steps, args.warmup, xt, wt, s)
     if not args.no_precision and args.only == "step":
         log("precision leg ...")
         result["precision"] = precision_leg(args.steps, args.warmup)
