@@ -249,9 +249,13 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
                         KernelSource& ks, std::string& err) {
     const int th = c.get("th"), tw = c.get("tw"), p = c.get("p"), q = c.get("q"), nb = c.get("nb");
     const int ds = c.get("ds"), layout = c.get("layout"), xpad = c.get("xpad"), wpad = c.get("wpad");
-    const int ud = c.get("ud"), xcd = c.get("xcd");
+    const int ud = c.get("ud"), xcd = c.get("xcd"), fsrc = c.get("fsrc");
     if (th < 1 || tw < 1 || p < 1 || q < 1 || nb < 1 || ds < 1 || xpad < 0 || wpad < 0 || ud < 1) {
         err = "direct: every knob must be positive"; return false;
+    }
+    if (fsrc != 0 && fsrc != 1) { err = "direct: fsrc is 0 or 1"; return false; }
+    if (fsrc && (ds != 1 || (th * (tw / p)) % 64 != 0)) {
+        err = "direct: scalar weights (fsrc=1) need ds=1 and th*tw/p a multiple of 64"; return false;
     }
     if (tw % p) { err = "direct: p must divide tw"; return false; }
     if (nb % q) { err = "direct: q must divide nb"; return false; }
@@ -266,7 +270,7 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
     const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
     const int trr = th + d.fh - 1, tcc = tw + d.fw - 1;
     const long tile = layout == 0 ? (long)trr * (tcc * d.D + xpad) : (long)d.D * trr * (tcc + xpad);
-    const long lds = (tile + (long)d.fw * d.D * (nb + wpad)) * 4;
+    const long lds = (tile + (fsrc ? 0L : (long)d.fw * d.D * (nb + wpad))) * 4;
     if (lds > di.lds_per_block) { err = "direct: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
     const long grid = (long)cdiv(wo, tw) * cdiv(ho, th) * cdiv(d.N, nb) * d.batch;
     if (grid <= 0 || grid > 0x7fffffffL) { err = "direct: grid out of range"; return false; }
@@ -285,6 +289,10 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
     opt(ks.options, "NB", nb); opt(ks.options, "DS", ds); opt(ks.options, "LAYOUT", layout);
     opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad); opt(ks.options, "UD", ud);
     opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    if (fsrc) {
+        opt(ks.options, "FSRC", 1);
+        opt(ks.options, "NPAD", cdiv(d.N, nb) * nb);
+    }
     return true;
 }
 
@@ -357,7 +365,7 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
 static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
         {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd"}},
-        {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd"}},
+        {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf"}},
     };
     auto it = keys.find(c.algo);
@@ -384,6 +392,17 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
         if (c.algo == "direct") {
             if (dt != 0) { err = "the direct kernel is fp32 only"; return false; }
             if (!geom_direct(c, d, di, rb.main_geom, rb.main, err)) return false;
+            if (c.get("fsrc")) {
+                // tap-major copy of the filters for the scalar loads
+                const int npad = cdiv(d.N, c.get("nb")) * c.get("nb");
+                KernelSource ks = util_source("fbcorr_transpose_filters", "TRANSPOSE_FILTERS");
+                opt(ks.options, "N", d.N); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw);
+                opt(ks.options, "D", d.D); opt(ks.options, "NPAD", npad);
+                rb.aux.push_back(ks);
+                rb.aux_geom.push_back(LaunchGeom{cdivl(K * npad, 256), 1, 256, 0});
+                rb.ws_lowp_w = 0;
+                rb.ws_bytes = align256((size_t)K * npad * 4);
+            }
         } else if (c.algo == "igemm") {
             if (!geom_igemm("fbcorr_fwd_igemm", c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di,
                             rb.main_geom, rb.main, err))

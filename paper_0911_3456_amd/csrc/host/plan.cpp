@@ -104,7 +104,14 @@ fbcorr_status run_forward(Plan* p, const RoleExec& ex, const float* x, const flo
     const void* wt = w;
     const float* unscale = nullptr;
     fbcorr_status st;
-    if (!ex.aux.empty()) {
+    if (!ex.aux.empty() && rb.cfg.algo == "direct") {
+        // scalar-weight direct kernel: tap-major copy of the filters
+        float* wtt = (float*)ws;
+        void* args[] = {(void*)&w, &wtt};
+        st = launch(ex.aux[0], rb.aux_geom[0], s, args);
+        if (st != FBCORR_OK) return st;
+        w = wtt;
+    } else if (!ex.aux.empty()) {
         // low precision: scale, round and pack the filters into the workspace
         char* base = (char*)ws;
         void* wq = base + rb.ws_lowp_w;

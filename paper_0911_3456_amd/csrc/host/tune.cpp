@@ -131,6 +131,10 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                         const int thr = th * (tw / p) * (c.v["nb"] / q) * c.v["ds"];
                                         if (thr < 64 || thr > 1024 || thr % 64) continue;
                                         add(out, seen, c);
+                                        if (c.v["ds"] == 1 && (th * (tw / p)) % 64 == 0) {
+                                            c.v["fsrc"] = 1;           // weights by scalar loads
+                                            add(out, seen, c);
+                                        }
                                     }
         }
     } else {

@@ -4,7 +4,12 @@
 //
 // One workgroup computes an output tile of TH x TW pixels for NB filters.
 // The input tile with its (FH-1, FW-1) halo is staged once in LDS; the
-// filter slice for one filter row u is staged per step.  Each thread
+// filter slice for one filter row u is staged per step (FSRC = 0), or, with
+// FSRC = 1, every wave's threads share one filter group and read their
+// weights with scalar loads from a tap-major copy of the filters (w then
+// points at that copy, wt[((u*FW + v)*D + d)*NPAD + n]): no LDS for the
+// weights and no barrier per filter row; the weights reach the FMAs as
+// scalar operands.  Each thread
 // accumulates P horizontally adjacent pixels x Q filters in registers; for a
 // fixed (u, d) its P+FW-1 inputs are read once and reused across the FW taps
 // (the sliding window), and the Q weights of a tap are one broadcast read
@@ -21,6 +26,8 @@
 //            LAYOUT (0: tile [row][col][d], 1: tile [d][row][col])
 //            XPAD WPAD (LDS padding)  UD (unroll of the channel loop)
 //            XCDMAP (XCD-aware workgroup order)
+//            FSRC (filter source: 0 LDS slice, 1 scalar loads; NPAD = filter
+//            count of the tap-major copy)
 //   EPILOGUE(v, c)  optional elementwise function of an output value v and
 //            its filter c, applied before the store (a fused nonlinearity)
 #ifndef __HIPCC_RTC__
@@ -51,6 +58,11 @@
 #define WPAD FB_WPAD
 #define UD FB_UD
 #define XCDMAP FB_XCDMAP
+#ifdef FB_FSRC
+#define FSRC FB_FSRC
+#else
+#define FSRC 0
+#endif
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -76,12 +88,18 @@ static_assert(NB % Q == 0, "Q must divide NB");
 static_assert(Q % 4 == 0, "Q must be a multiple of 4");
 static_assert(D % DS == 0, "DS must divide D");
 static_assert(NBS % 4 == 0, "filter rows must stay 16-byte aligned");
+#if FSRC
+static_assert(DS == 1 && NPG % 64 == 0, "scalar weights need one filter group per wave");
+#define NPAD FB_NPAD
+#endif
 
 extern "C" __global__ void __launch_bounds__(NTHREADS)
 fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* __restrict__ y)
 {
     __shared__ __attribute__((aligned(16))) float tile[TILE_ELEMS];
+#if !FSRC
     __shared__ __attribute__((aligned(16))) float wsl[WSL_ELEMS];
+#endif
 
     const int tid = threadIdx.x;
     const int ds = tid % DS;
@@ -139,8 +157,15 @@ fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* _
 #pragma unroll
         for (int q = 0; q < Q; ++q) acc[p][q] = 0.f;
 
+#if FSRC
+    __syncthreads();
+    // The wave's filter group, made explicitly uniform so that its weight
+    // addresses are scalar.
+    const int fgu = __builtin_amdgcn_readfirstlane(fg);
+#endif
 #pragma unroll 1
     for (int u = 0; u < FH; ++u) {
+#if !FSRC
         __syncthreads();
         // Filter slice for row u, stored [v][d][filter] so that the Q weights
         // of one tap are contiguous.
@@ -150,6 +175,7 @@ fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* _
             wsl[vd * NBS + f] = (n < N) ? w[((long)n * FH + u) * FW * D + vd] : 0.f;
         }
         __syncthreads();
+#endif
 
 #pragma unroll UD
         for (int dd = 0; dd < D / DS; ++dd) {
@@ -159,7 +185,11 @@ fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* _
             for (int e = 0; e < P + FW - 1; ++e) xr[e] = tile[TIDX(d, ti + u, tj + e)];
 #pragma unroll
             for (int v = 0; v < FW; ++v) {
+#if FSRC
+                const float* wp = w + ((long)(u * FW + v) * D + d) * NPAD + n0 + fgu * Q;
+#else
                 const float* wp = wsl + (v * D + d) * NBS + fg * Q;
+#endif
 #pragma unroll
                 for (int q4 = 0; q4 < Q; q4 += 4) {
                     const f32x4 wv = *(const f32x4*)(wp + q4);

@@ -13,8 +13,12 @@
 //                        bf16 (LOWP=1) or fp16 (LOWP=2), unscale[n] = 2^e_n
 //                        (an all-zero filter gets e_n = 0).
 //   fbcorr_fill_int      integer-valued pattern in [-R, R] (tuner gate data).
+//   fbcorr_transpose_filters  wt[((u*FW + v)*D + d)*NPAD + n] = w[n,u,v,d]
+//                        (zero for N <= n < NPAD): the filters of one tap
+//                        contiguous, for the direct kernel's scalar loads.
 //
-// Compile-time constants: L NP RS LANES (sum); N FH FW D (flip, pack); LOWP (pack).
+// Compile-time constants: L NP RS LANES (sum); N FH FW D (flip, pack,
+// transpose); LOWP (pack); NPAD (transpose).
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -159,5 +163,17 @@ fbcorr_fill_int(float* __restrict__ out, long n, unsigned seed, int R)
     unsigned hsh = (unsigned)i * 0x9E3779B1u ^ (unsigned)(i >> 32) ^ seed;
     hsh ^= hsh >> 15; hsh *= 0x85EBCA77u; hsh ^= hsh >> 13; hsh *= 0xC2B2AE3Du; hsh ^= hsh >> 16;
     out[i] = (float)((int)(hsh % (unsigned)(2 * R + 1)) - R);
+}
+#endif
+
+#ifdef FB_TRANSPOSE_FILTERS
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_transpose_filters(const float* __restrict__ w, float* __restrict__ wt)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;    // over FH*FW*D*NPAD
+    if (e >= (long)FH * FW * D * FB_NPAD) return;
+    const int n = (int)(e % FB_NPAD);
+    const long k = e / FB_NPAD;                              // (u*FW + v)*D + d
+    wt[e] = n < N ? w[(long)n * FH * FW * D + k] : 0.f;
 }
 #endif
