@@ -410,6 +410,22 @@ fbcorr_status fbnn_search(fbnn_plan_t plan, const uint8_t* targets, const uint8_
     if (timing) {
         std::lock_guard<std::mutex> lk(p->mu);
         p->pending.push_back(ev);
+        if (p->pending.size() > kMaxPendingEvents) {    // fold the oldest half into the totals
+            const size_t half = p->pending.size() / 2;
+            for (size_t i = 0; i < half; ++i) {
+                auto& e = p->pending[i];
+                hipEventSynchronize(e[3]);
+                for (int q = 0; q < 3; ++q) {
+                    float t = 0.f;
+                    if (hipEventElapsedTime(&t, e[q], e[q + 1]) == hipSuccess) {
+                        p->acc_ms[q] += t;
+                        p->acc_calls[q] += 1;
+                    }
+                }
+                for (auto x : e) hipEventDestroy(x);
+            }
+            p->pending.erase(p->pending.begin(), p->pending.begin() + half);
+        }
     }
     return st;
     FBC_API_END

@@ -95,7 +95,24 @@ void timing_end(Plan* p, int role, hipStream_t s, hipEvent_t a) {
     hipEventCreate(&b);
     hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(p->mu);
-    p->pending[role].push_back({a, b});
+    auto& pend = p->pending[role];
+    pend.push_back({a, b});
+    // Keep the number of live events bounded when the totals are not read:
+    // fold the completed half into the running totals.
+    if (pend.size() > kMaxPendingEvents) {
+        const size_t half = pend.size() / 2;
+        for (size_t i = 0; i < half; ++i) {
+            hipEventSynchronize(pend[i].second);
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pend[i].first, pend[i].second) == hipSuccess) {
+                p->acc_ms[role] += t;
+                p->acc_calls[role] += 1;
+            }
+            hipEventDestroy(pend[i].first);
+            hipEventDestroy(pend[i].second);
+        }
+        pend.erase(pend.begin(), pend.begin() + half);
+    }
 }
 
 fbcorr_status run_forward(Plan* p, const RoleExec& ex, const float* x, const float* w, float* y, void* ws,

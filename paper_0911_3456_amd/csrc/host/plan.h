@@ -13,6 +13,9 @@ struct RoleExec {
 
 struct BatchedState;   // batched.cpp
 
+// Timing events kept per role before the oldest are folded into the totals.
+constexpr size_t kMaxPendingEvents = 1024;
+
 struct Plan {
     fbcorr_desc desc{};
     int device = 0;
