@@ -364,7 +364,7 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
 
 static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
-        {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd"}},
+        {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf"}},
     };
@@ -404,6 +404,7 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
                 rb.ws_bytes = align256((size_t)K * npad * 4);
             }
         } else if (c.algo == "igemm") {
+            if (c.get("flip")) { err = "flip applies to the input-gradient role only"; return false; }
             if (!geom_igemm("fbcorr_fwd_igemm", c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di,
                             rb.main_geom, rb.main, err))
                 return false;
@@ -430,6 +431,11 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
         if (!geom_igemm("fbcorr_dx_igemm", c, d.batch, ho, wo, d.N, d.D, d.fh, d.fw, d.fh - 1, d.fw - 1, 0, di,
                         rb.main_geom, rb.main, err))
             return false;
+        if (c.get("flip")) {
+            // the flip happens while staging: the kernel reads the forward bank
+            rb.main.options.push_back("-DFB_FLIPW");
+            return true;
+        }
         KernelSource ks = util_source("fbcorr_flip_filters", "FLIP_FILTERS");
         opt(ks.options, "N", d.N); opt(ks.options, "FH", d.fh); opt(ks.options, "FW", d.fw); opt(ks.options, "D", d.D);
         rb.aux.push_back(ks);

@@ -155,12 +155,16 @@ fbcorr_status run_forward(Plan* p, const RoleExec& ex, const float* x, const flo
 fbcorr_status run_backward_x(Plan* p, const RoleExec& ex, const float* w, const float* dy, float* dx, void* ws,
                              hipStream_t s) {
     const RoleBuild& rb = ex.build;
-    float* wf = (float*)ws;
-    void* a0[] = {(void*)&w, (void*)&wf};
-    fbcorr_status st = launch(ex.aux[0], rb.aux_geom[0], s, a0);
-    if (st != FBCORR_OK) return st;
+    const float* wfc = w;                   // fused flip: the kernel reads w itself
+    if (!ex.aux.empty()) {
+        float* wf = (float*)ws;
+        void* a0[] = {(void*)&w, (void*)&wf};
+        fbcorr_status st = launch(ex.aux[0], rb.aux_geom[0], s, a0);
+        if (st != FBCORR_OK) return st;
+        wfc = wf;
+    }
+    fbcorr_status st;
     const float* unscale = nullptr;
-    const float* wfc = wf;
     hipEvent_t ev;
     timing_begin(p, FBCORR_ROLE_BACKWARD_X, s, ev);
     void* a1[] = {(void*)&dy, (void*)&wfc, (void*)&unscale, (void*)&dx};

@@ -84,7 +84,10 @@ def test_one_gradient_at_a_time():
 BX_CFGS = ["mf=16 kc=4 s=2 mr=4 mt=2 nt=1 wm=2 wn=1 ks=4", "mf=16 kc=8 s=1 mr=2 mt=1 nt=1 wm=2 wn=1 ks=2",
            "kc=4 s=4 mr=4 mt=1 nt=1 wm=1 wn=1 ks=4", "kc=4 s=4 mr=2 mt=2 nt=1 wm=1 wn=1 ks=2 ustage=3",
            "kc=8 s=2 mr=4 mt=1 nt=1 wm=2 wn=1 ks=3", "kc=8 s=4 mt=1 nt=1 wm=4 wn=1", "kc=8 s=2 mr=1 ks=1 mt=2 nt=1 wm=2 wn=1 ustage=3",
-           "kc=4 s=8 mt=1 nt=1 wm=2 wn=1 xcd=0", "kc=8 s=1 mt=1 nt=1 wm=4 wn=1"]
+           "kc=4 s=8 mt=1 nt=1 wm=2 wn=1 xcd=0", "kc=8 s=1 mt=1 nt=1 wm=4 wn=1",
+           # the flip fused into the staging
+           "mf=16 kc=16 s=2 mr=1 mt=1 nt=1 wm=8 wn=1 ks=2 ustage=3 flip=1",
+           "kc=4 s=4 mr=4 mt=1 nt=1 wm=1 wn=1 ks=4 flip=1", "kc=8 s=2 mr=4 mt=1 nt=1 wm=2 wn=1 ks=3 flip=1"]
 BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=0",
            "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=1", "rh=2 rw=32 nw=8 tpb=14 np=300 pf=1",
            "rh=2 rw=32 nw=8 tpb=21 np=64 pf=2", "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=2",
@@ -288,3 +291,21 @@ def test_overlapped_backward_matches_sequential():
         res.append((host(dx), host(dw)))
     np.testing.assert_array_equal(res[0][0], res[1][0])
     np.testing.assert_array_equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("shape", [(1, 30, 33, 3, 7, 5, 4), (2, 21, 26, 5, 16, 3, 3), (1, 40, 40, 12, 33, 7, 7)])
+def test_fused_flip_ragged_channels(shape):
+    """The fused flip with channel counts that are not multiples of four
+    (one channel per staged item) and ragged tiles: exact on integers."""
+    need_gpu()
+    from paper_0911_3456_amd import Plan
+    s = wl.Shape(*shape)
+    x, w, rng = wl.draw_integer(s, seed=61, xmax=2, wmax=2)
+    g = rng.integers(-2, 3, size=(s.batch, s.Ho, s.Wo, s.N)).astype(np.float32)
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw)
+    plan.set_config("backward_x", plan.get_config("backward_x") + " flip=1")
+    assert "flip=1" in plan.get_config("backward_x")
+    xt, wt, gt = to_dev(x, w, g)
+    dx, _ = plan.backward(xt, wt, gt, need_dw=False)
+    rdx, _ = oracle.backward(x, w, g, want_dw=False)
+    np.testing.assert_array_equal(host(dx), rdx.astype(np.float32))
