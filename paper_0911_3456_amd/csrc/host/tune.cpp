@@ -103,6 +103,10 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                     c.v["xpad"] = xp[pad] * unit;
                                     c.v["wpad"] = wp[pad] * unit;
                                     grid.push_back(c);
+                                    if (role == FBCORR_ROLE_BACKWARD_X) {
+                                        c.v["flip"] = 1;    // flip fused into the staging
+                                        grid.push_back(c);
+                                    }
                                 }
         // a coarse, deterministic subsample of the full grid (Fisher-Yates
         // with a fixed LCG), the default first
