@@ -146,7 +146,8 @@ Config default_dw(const fbcorr_desc& d, int cus) {
     const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
     const long nchunks = (long)d.batch * cdiv(ho, 2) * cdiv(wo, 32);
     const int np = (int)std::max<long>(1, std::min<long>(nchunks, std::max(1, cus) / 2));
-    c.v = {{"rh", 2}, {"rw", 32}, {"nw", 8}, {"tpb", tpb}, {"np", np}, {"gpad", 4}, {"xpad", 4}, {"pf", 1}};
+    c.v = {{"rh", 2}, {"rw", 32}, {"nw", 8}, {"tpb", tpb}, {"np", np}, {"gpad", 4}, {"xpad", 4}, {"pf", 1},
+           {"bal", 0}, {"unr", 4}};
     return c;
 }
 
@@ -299,7 +300,8 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
 static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di, LaunchGeom& g,
                     KernelSource& ks, int& np_out, std::string& err) {
     const int rh = c.get("rh"), rw = c.get("rw"), nw = c.get("nw"), tpb = c.get("tpb");
-    const int gpad = c.get("gpad"), xpad = c.get("xpad"), pf = c.get("pf");
+    const int gpad = c.get("gpad"), xpad = c.get("xpad"), pf = c.get("pf"), bal = c.get("bal");
+    const int unr = c.v.count("unr") ? c.get("unr") : 4;
     int np = c.get("np");
     if (rh < 1 || rw < 1 || nw < 1 || tpb < 1 || gpad < 0 || xpad < 0 || np < 1) {
         err = "dw: every knob must be positive"; return false;
@@ -307,15 +309,23 @@ static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di,
     if ((rh * rw) % 2) { err = "dw: rh*rw must be even"; return false; }
     const int tiles = dw_tiles(d);
     const int tpb_eff = std::min(tpb, tiles);
-    if (cdiv(tpb_eff, nw) > 8) { err = "dw: more than 8 accumulator tiles per wave"; return false; }
+    if (bal < 0 || bal > 1) { err = "dw: bal must be 0 or 1"; return false; }
+    if (unr < 0 || unr > 64) { err = "dw: unr must be 0 (complete) or 1..64"; return false; }
+    // accumulator slots per wave: round-robin tiles, or full rounds + two
+    // slots for the left-over tiles split by pixels
+    const int slots = bal ? tpb_eff / nw + 2 : cdiv(tpb_eff, nw);
+    if (slots > 8) { err = "dw: more than 8 accumulator tiles per wave"; return false; }
     const int threads = nw * 64;
     if (threads > std::min(1024, di.max_threads)) { err = "dw: too many threads"; return false; }
     const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
     const int npad = cdiv(d.N, 32) * 32;
     const int pc = rh * rw;
     if (pf < 0 || pf > 2) { err = "dw: pf must be 0, 1 or 2"; return false; }
-    const long lds = (pf == 2 ? 2 : 1) *
-                     ((long)pc * (npad + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
+    const long stage = (pf == 2 ? 2 : 1) *
+                       ((long)pc * (npad + gpad) + (long)(rh + d.fh - 1) * ((rw + d.fw - 1) * d.D + xpad)) * 4;
+    // with bal the staging memory is reused for the left-over slots (two
+    // 32x32 fp32 tiles per wave)
+    const long lds = std::max(stage, bal ? (long)nw * 2 * 1024 * 4 : 0L);
     if (lds > di.lds_per_block) { err = "dw: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
     const long prefetch_regs = pf ? (cdivl((long)pc * npad, threads) + cdivl((long)(rh + d.fh - 1) * (rw + d.fw - 1) * d.D, threads)) : 0;
     if (prefetch_regs > 96) { err = "dw: prefetch needs too many registers"; return false; }
@@ -337,6 +347,8 @@ static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di,
     opt(ks.options, "RH", rh); opt(ks.options, "RW", rw); opt(ks.options, "NW", nw); opt(ks.options, "TPB", tpb_eff);
     opt(ks.options, "NP", np); opt(ks.options, "GPAD", gpad); opt(ks.options, "XPAD", xpad);
     opt(ks.options, "PF", pf);
+    if (bal) opt(ks.options, "BAL", bal);
+    opt(ks.options, "UNR", unr);
     return true;
 }
 
@@ -366,7 +378,7 @@ static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
         {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
-        {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf"}},
+        {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }

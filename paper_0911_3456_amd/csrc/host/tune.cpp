@@ -145,18 +145,37 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         const Config base = default_config(d, role, DeviceInfo{"gfx950", 256, 160 * 1024, 1024});
         const int tiles = ((d.N + 31) / 32) * ((d.fh * d.fw * d.D + 31) / 32);
         std::vector<Config> grid;
+        // chunk widths: powers of two, and the divisors of the output width
+        // that leave no ragged chunk column
+        std::vector<int> rws = {32, 64};
+        const int wo = d.W - d.fw + 1;
+        for (int k = 1; k <= 16; ++k)
+            if (wo % k == 0 && wo / k >= 16 && wo / k <= 128 && wo / k != 32 && wo / k != 64) rws.push_back(wo / k);
+        const int ho = d.H - d.fh + 1;
         for (int rh : {1, 2, 4})
-            for (int rw : {32, 64})
+            for (int rw : rws) {
+                if ((rh * rw) % 2) continue;
+                // partial counts: fixed fractions of the chip, and those that
+                // give every workgroup the same number of chunks
+                const long nchunks = (long)d.batch * cdiv(ho, rh) * cdiv(wo, rw);
+                std::vector<int> nps = {32, 64, 128, 256};
+                for (int k = 1; k <= 8; ++k)
+                    if (nchunks % k == 0 && nchunks / k >= 32 && nchunks / k <= 512 &&
+                        std::find(nps.begin(), nps.end(), (int)(nchunks / k)) == nps.end())
+                        nps.push_back((int)(nchunks / k));
                 for (int nw : {2, 4, 6, 8, 12, 14, 16})
                     for (int split : {1, 2, 3, 4, 6})
-                        for (int np : {32, 64, 128, 256})
-                            for (int pf : {0, 1, 2}) {
-                                Config c = base;
-                                c.v["rh"] = rh; c.v["rw"] = rw; c.v["nw"] = nw;
-                                c.v["tpb"] = (tiles + split - 1) / split;
-                                c.v["np"] = np; c.v["pf"] = pf;
-                                grid.push_back(c);
-                            }
+                        for (int np : nps)
+                            for (int pf : {0, 1, 2})
+                                for (int bal : {0, 1})
+                                    for (int unr : {0, 4}) {
+                                        Config c = base;
+                                        c.v["rh"] = rh; c.v["rw"] = rw; c.v["nw"] = nw;
+                                        c.v["tpb"] = (tiles + split - 1) / split;
+                                        c.v["np"] = np; c.v["pf"] = pf; c.v["bal"] = bal; c.v["unr"] = unr;
+                                        grid.push_back(c);
+                                    }
+            }
         uint64_t st = 0x2545F4914F6CDD1Dull;
         for (size_t i = grid.size(); i > 1; --i) {
             st = st * 6364136223846793005ull + 1442695040888963407ull;

@@ -18,12 +18,27 @@
 // chunk costs one barrier.  The B fragment of a lane for tap column q is the input value
 // at its pixel offset by (u, v), channel d.
 //
+//
+// Balanced mode (BAL).  Dealing TPB tiles round-robin gives some waves one
+// tile more than others, and since every chunk ends at a barrier the chunk
+// takes as long as the busiest SIMD.  With BAL the workgroup's tiles are dealt
+// in R = NTW / NW full rounds only; the RM = NTW % NW tiles left over are cut
+// by pixel pairs instead: their RM * PC/2 (tile, step) units are split into
+// NW contiguous ranges, one per wave, so every wave issues the same number of
+// products per chunk.  A range touches at most two of those tiles (two extra
+// accumulator slots); at the end the slots of each left-over tile are added
+// in LDS in wave order (a fixed order, so results do not depend on timing).
+//
 // Compile-time constants (FB_<name>):
 //   problem  BATCH FH FW D N H W HO WO
 //   tiling   RH RW (pixel chunk)  NW (waves)  TPB (tiles per workgroup)
 //            NP (partials = workgroup columns)  GPAD XPAD (LDS padding)
 //            PF (0: none, 1: register prefetch of the next chunk,
 //                2: register prefetch + double-buffered LDS)
+//            BAL (0: round-robin tiles, 1: balanced split of the left-over
+//                 tiles, see above)
+//            UNR (unrolling of the per-chunk step loop: 0 = complete, which
+//                 turns every LDS address into an immediate offset; k = by k)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -49,6 +64,16 @@
 #define GPAD FB_GPAD
 #define XPAD FB_XPAD
 #define PF FB_PF
+#ifdef FB_BAL
+#define BAL FB_BAL
+#else
+#define BAL 0
+#endif
+#ifdef FB_UNR
+#define UNR FB_UNR
+#else
+#define UNR 4
+#endif
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -81,27 +106,66 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 static_assert(PC % 2 == 0, "pixel chunk must be even");
 
 #define NBUF (PF == 2 ? 2 : 1)
+#define HS (PC / 2)                      // MFMA steps per chunk (two pixels each)
+#if BAL
+#define RFULL (TPB / NW)                 // full rounds of tiles
+#define NSLOT (RFULL + 2)                // + two slots for left-over tiles
+#else
+#define RFULL TPW
+#define NSLOT TPW
+#endif
+#define STAGE_FLOATS (NBUF * (PC * GST + XR * XRS))
+#define RED_FLOATS (BAL ? NW * 2 * 16 * 64 : 0)
+#define LDS_FLOATS (STAGE_FLOATS > RED_FLOATS ? STAGE_FLOATS : RED_FLOATS)
 
 extern "C" __global__ void __launch_bounds__(NTHREADS)
 fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
                   float* __restrict__ part)
 {
-    __shared__ __attribute__((aligned(16))) float gl_all[NBUF][PC * GST];
-    __shared__ __attribute__((aligned(16))) float xl_all[NBUF][XR * XRS];
+    // Staging buffers (dy chunk, input tile; two of each with PF = 2); with
+    // BAL the same memory holds the left-over slots for the final sum.
+    __shared__ __attribute__((aligned(16))) float lds_raw[LDS_FLOATS];
+    float* const gl_base = lds_raw;
+    float* const xl_base = lds_raw + NBUF * PC * GST;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l32 = lane & 31, h = lane >> 5;
     const int g = blockIdx.x;
 
-    // This wave's tiles: row offset into the dy tile and LDS offset of tap q
-    // relative to the pixel's own position (0 for padding columns: an
-    // in-bounds read whose result is never stored).
-    int arow[TPW], qoff[TPW], tq[TPW], tn[TPW];
-    bool tval[TPW];
+    // Slot k < RFULL holds tile wave + k*NW of the workgroup.  With BAL,
+    // slots RFULL and RFULL + 1 hold left-over tiles r0 and r0 + 1 for the
+    // steps [slo[j], shi[j]) of every chunk.
+    int lt_of[NSLOT];
+#if BAL
+    const int ntw = (TILES - (int)blockIdx.y * TPB) < TPB ? TILES - (int)blockIdx.y * TPB : TPB;
+    const int rfull = ntw / NW, rm = ntw % NW;
+    const int units = rm * HS;
+    const int lo = wave * units / NW, hi = (wave + 1) * units / NW;
+    const int r0 = lo / HS;
+    int slo[2], shi[2];
+    slo[0] = lo - r0 * HS;
+    shi[0] = hi - r0 * HS < HS ? hi - r0 * HS : HS;
+    slo[1] = 0;
+    shi[1] = hi - (r0 + 1) * HS > 0 ? hi - (r0 + 1) * HS : 0;
 #pragma unroll
-    for (int k = 0; k < TPW; ++k) {
-        const int lt = wave + k * NW;
+    for (int k = 0; k < RFULL; ++k) lt_of[k] = k < rfull ? wave + k * NW : TPB;
+    lt_of[RFULL] = slo[0] < shi[0] ? rfull * NW + r0 : TPB;
+    lt_of[RFULL + 1] = slo[1] < shi[1] ? rfull * NW + r0 + 1 : TPB;
+#else
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) lt_of[k] = wave + k * NW;
+#endif
+
+    // Per slot: row offset into the dy tile and LDS offset of tap q relative
+    // to the pixel's own position (0 for padding columns and empty slots: an
+    // in-bounds read whose result is never stored).
+    int arow[NSLOT], qoff[NSLOT], tq[NSLOT], tn[NSLOT];
+    bool tval[NSLOT];
+#pragma unroll
+    for (int k = 0; k < NSLOT; ++k) {
+        const int lt = lt_of[k];
         const int t = blockIdx.y * TPB + lt;
         tval[k] = lt < TPB && t < TILES;
         const int rt = tval[k] ? t % NROWT : 0, ct = tval[k] ? t / NROWT : 0;
@@ -117,9 +181,9 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
         }
     }
 
-    f32x16 acc[TPW];
+    f32x16 acc[NSLOT];
 #pragma unroll
-    for (int k = 0; k < TPW; ++k)
+    for (int k = 0; k < NSLOT; ++k)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
 
@@ -152,8 +216,8 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
         }
     };
     auto store = [&](int b) {
-        float* gl = gl_all[b];
-        float* xl = xl_all[b];
+        float* gl = gl_base + b * (PC * GST);
+        float* xl = xl_base + b * (XR * XRS);
 #pragma unroll
         for (int r = 0; r < GPER; ++r) {
             const int e = tid + r * NTHREADS;
@@ -168,18 +232,23 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
 
     // The products of one staged chunk (LDS buffer b).
     auto compute = [&](int b) {
-        const float* gl = gl_all[b];
-        const float* xl = xl_all[b];
-        // Lane half h walks pixels [h*PC/2, (h+1)*PC/2) of the chunk.
-#pragma unroll 4
-        for (int t = 0; t < PC / 2; ++t) {
-            const int p = h * (PC / 2) + t;
+        const float* gl = gl_base + b * (PC * GST);
+        const float* xl = xl_base + b * (XR * XRS);
+        // Lane half h walks pixels [h*HS, (h+1)*HS) of the chunk.
+#if RFULL > 0
+#if UNR == 0
+#pragma unroll
+#else
+#pragma unroll UNR
+#endif
+        for (int t = 0; t < HS; ++t) {
+            const int p = h * HS + t;
             const int xo = (p / RW) * XRS + (p % RW) * D;
 #if SAMEROW
             const float a0 = gl[p * GST + arow[0]];
 #endif
 #pragma unroll
-            for (int k = 0; k < TPW; ++k) {
+            for (int k = 0; k < RFULL; ++k) {
 #if SAMEROW
                 const float a = a0;
 #else
@@ -189,6 +258,22 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
                 acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
             }
         }
+#endif
+#if BAL
+        // This wave's share of the left-over tiles.
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = RFULL + j;
+#pragma unroll 4
+            for (int t = slo[j]; t < shi[j]; ++t) {
+                const int p = h * HS + t;
+                const int xo = (p / RW) * XRS + (p % RW) * D;
+                const float a = gl[p * GST + arow[k]];
+                const float bb = xl[xo + qoff[k]];
+                acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
+            }
+        }
+#endif
     };
 
 #if PF == 2
@@ -232,7 +317,7 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
     // Partial sums: part[g][n][q] (zeros from workgroups without chunks).
     float* out = part + (long)g * N * QTOT;
 #pragma unroll
-    for (int k = 0; k < TPW; ++k) {
+    for (int k = 0; k < RFULL; ++k) {
         if (!tval[k]) continue;
         const int q = tq[k];
 #pragma unroll
@@ -241,4 +326,46 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
             if (n < N && q < QTOT) out[(long)n * QTOT + q] = acc[k][r];
         }
     }
+#if BAL
+    // Left-over tiles: every wave parks its two slots in LDS (the staging
+    // buffers are free once all waves are past their last chunk), then wave
+    // w < RM adds the slots holding left-over tile w in wave order.
+    __syncthreads();
+    float* red = lds_raw;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        if (tval[RFULL + j])
+#pragma unroll
+            for (int r = 0; r < 16; ++r) red[((wave * 2 + j) * 16 + r) * 64 + lane] = acc[RFULL + j][r];
+    __syncthreads();
+    if (wave < rm) {
+        f32x16 s;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) s[r] = 0.f;
+#pragma unroll 1
+        for (int w2 = 0; w2 < NW; ++w2) {
+            const int lo2 = w2 * units / NW, hi2 = (w2 + 1) * units / NW;
+            if (lo2 == hi2) continue;
+            const int r02 = lo2 / HS;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                // slot j of wave w2 covers tile r02 + j if its step range is non-empty
+                const int jlo = j == 0 ? lo2 - r02 * HS : 0;
+                const int jhi = j == 0 ? (hi2 - r02 * HS < HS ? hi2 - r02 * HS : HS)
+                                       : (hi2 - (r02 + 1) * HS > 0 ? hi2 - (r02 + 1) * HS : 0);
+                if (r02 + j != wave || jlo >= jhi) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) s[r] += red[((w2 * 2 + j) * 16 + r) * 64 + lane];
+            }
+        }
+        const int t = blockIdx.y * TPB + rfull * NW + wave;
+        const int rt = t % NROWT, ct = t / NROWT;
+        const int q = ct * 32 + l32;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = rt * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (n < N && q < QTOT) out[(long)n * QTOT + q] = s[r];
+        }
+    }
+#endif
 }

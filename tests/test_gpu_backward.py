@@ -91,7 +91,16 @@ BX_CFGS = ["mf=16 kc=4 s=2 mr=4 mt=2 nt=1 wm=2 wn=1 ks=4", "mf=16 kc=8 s=1 mr=2 
 BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=0",
            "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=1", "rh=2 rw=32 nw=8 tpb=14 np=300 pf=1",
            "rh=2 rw=32 nw=8 tpb=21 np=64 pf=2", "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=2",
-           "rh=4 rw=16 nw=14 tpb=42 np=7 pf=2"]
+           "rh=4 rw=16 nw=14 tpb=42 np=7 pf=2",
+           # balanced split of the left-over tiles: five left over, none left
+           # over, a wave range of odd length, a short last workgroup row
+           # with only left-over tiles, one full round plus one left over
+           "rh=2 rw=32 nw=8 tpb=21 np=64 pf=1 bal=1", "rh=4 rw=16 nw=14 tpb=42 np=7 pf=2 bal=1",
+           "rh=1 rw=62 nw=16 tpb=42 np=9 pf=1 bal=1", "rh=2 rw=30 nw=8 tpb=20 np=13 pf=0 bal=1",
+           "rh=1 rw=8 nw=4 tpb=5 np=40 pf=1 bal=1",
+           # step loop unrolled completely, or by a factor that leaves a rest
+           "rh=2 rw=30 nw=8 tpb=21 np=13 pf=1 unr=0", "rh=1 rw=62 nw=8 tpb=21 np=9 pf=2 bal=1 unr=0",
+           "rh=2 rw=16 nw=4 tpb=14 np=20 pf=0 unr=3"]
 
 
 @pytest.mark.parametrize("cfg", BX_CFGS)
