@@ -243,6 +243,7 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "KS", ksp); opt(ks.options, "DT", dt);
     opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad);
     opt(ks.options, "USTAGE", ustage); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    if (c.get("uunr")) opt(ks.options, "UUNR", 1);
     return true;
 }
 
@@ -376,7 +377,8 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
 
 static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
-        {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip"}},
+        {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip",
+                   "uunr"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr"}},
     };

@@ -107,6 +107,10 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                         c.v["flip"] = 1;    // flip fused into the staging
                                         grid.push_back(c);
                                     }
+                                    if (us > 1 && !lp) {
+                                        c.v["uunr"] = 1;    // filter rows of a stage unrolled
+                                        grid.push_back(c);
+                                    }
                                 }
         // a coarse, deterministic subsample of the full grid (Fisher-Yates
         // with a fixed LCG), the default first

@@ -87,7 +87,10 @@ BX_CFGS = ["mf=16 kc=4 s=2 mr=4 mt=2 nt=1 wm=2 wn=1 ks=4", "mf=16 kc=8 s=1 mr=2 
            "kc=4 s=8 mt=1 nt=1 wm=2 wn=1 xcd=0", "kc=8 s=1 mt=1 nt=1 wm=4 wn=1",
            # the flip fused into the staging
            "mf=16 kc=16 s=2 mr=1 mt=1 nt=1 wm=8 wn=1 ks=2 ustage=3 flip=1",
-           "kc=4 s=4 mr=4 mt=1 nt=1 wm=1 wn=1 ks=4 flip=1", "kc=8 s=2 mr=4 mt=1 nt=1 wm=2 wn=1 ks=3 flip=1"]
+           "kc=4 s=4 mr=4 mt=1 nt=1 wm=1 wn=1 ks=4 flip=1", "kc=8 s=2 mr=4 mt=1 nt=1 wm=2 wn=1 ks=3 flip=1",
+           # filter rows of a stage unrolled (stages of 3, and of 2 with a ragged last stage)
+           "mf=16 kc=16 s=2 mr=1 mt=1 nt=1 wm=8 wn=1 ks=2 ustage=3 flip=1 uunr=1",
+           "kc=4 s=4 mr=2 mt=2 nt=1 wm=1 wn=1 ks=2 ustage=2 uunr=1"]
 BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=0",
            "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=1", "rh=2 rw=32 nw=8 tpb=14 np=300 pf=1",
            "rh=2 rw=32 nw=8 tpb=21 np=64 pf=2", "rh=1 rw=64 nw=2 tpb=8 np=1 gpad=0 xpad=0 pf=2",

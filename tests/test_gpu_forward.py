@@ -96,6 +96,10 @@ IGEMM_CFGS = [
     "kc=8 s=1 mt=1 nt=1 wm=2 wn=2 xpad=0 wpad=0",
     "kc=8 s=2 mt=2 nt=1 wm=2 wn=2",
     "kc=2 s=4 mt=1 nt=1 wm=4 wn=1 xcd=0",
+    # filter rows of a stage unrolled; 9 rows in stages of 3, and of 4 (the
+    # last stage ragged)
+    "kc=8 s=1 mt=2 nt=2 wm=2 wn=1 ustage=3 uunr=1",
+    "mf=16 kc=4 s=2 mr=2 mt=1 nt=1 wm=2 wn=2 ks=2 ustage=4 uunr=1",
 ]
 
 
