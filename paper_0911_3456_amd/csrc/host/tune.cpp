@@ -74,7 +74,10 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         const int shapes[][4] = {{1, 1, 4, 1}, {1, 2, 4, 1}, {2, 1, 2, 2}, {2, 2, 2, 1}, {1, 2, 2, 2},
                                  {2, 2, 4, 1}, {1, 4, 4, 1}, {2, 2, 2, 2}, {4, 2, 1, 1}, {1, 1, 8, 1},
                                  {1, 1, 1, 1}, {2, 1, 1, 1}, {1, 2, 1, 1}, {2, 2, 1, 1}, {1, 1, 2, 1},
-                                 {2, 4, 2, 1}, {4, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {2, 4, 4, 1}};
+                                 {2, 4, 2, 1}, {4, 2, 2, 1}, {4, 4, 1, 1}, {4, 4, 2, 1}, {2, 4, 4, 1},
+                                 // 512-pixel workgroups: each staged filter slice serves twice the
+                                 // products (16-bit operands, where the filter staging dominates)
+                                 {2, 2, 8, 1}, {4, 1, 4, 1}, {1, 2, 16, 1}};
         std::vector<Config> grid;
         for (int kc : kcs)
             for (int s : ss)
