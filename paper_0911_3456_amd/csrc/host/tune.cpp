@@ -86,7 +86,7 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                     for (auto& sh : shapes)
                         for (int ksp : {1, 2, 4})
                             for (int us : {1, 3})
-                                for (int pad : {0, 1, 2, 3}) {
+                                for (int pad : {0, 1, 2, 3, 4}) {
                                     Config c = base;
                                     c.v["mf"] = mf;
                                     c.v["kc"] = kc;
@@ -102,7 +102,7 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                     c.v["ustage"] = us;
                                     // LDS row padding (bank-conflict avoidance), in whole vectors
                                     const int unit = lp ? 8 : 4;
-                                    const int xp[] = {0, 1, 2, 3}, wp[] = {0, 1, 0, 3};
+                                    const int xp[] = {0, 1, 2, 3, 3}, wp[] = {0, 1, 0, 3, 1};
                                     c.v["xpad"] = xp[pad] * unit;
                                     c.v["wpad"] = wp[pad] * unit;
                                     grid.push_back(c);
