@@ -5,7 +5,8 @@
 // variants (Sec. 4.2: generate code for exactly one purpose): the
 // implicit-GEMM body section is pasted once per key with that key's constants
 // substituted and the image extents left run-time, followed by a dispatch
-// loop.  At plan time the host builds a work table of (variant, image, tile)
+// loop.  Each body stays a function of its own (not inlined into the loop),
+// so registers are allocated per variant.  At plan time the host builds a work table of (variant, image, tile)
 // items sorted by cost, largest first; at run time each persistent
 // workgroup takes the next item from an integer counter until the table is
 // exhausted.  The launch (a counter-reset kernel plus the persistent kernel)
@@ -127,8 +128,10 @@ static bool generate(BatchedState& st, const DeviceInfo& di, KernelSource& ks, s
     src << "\n#define MAXLDS " << ((maxlds + 15) / 16 * 16) << "\n";
     src << R"KSRC(
 // Dispatch: each workgroup takes (variant, image, tile) items from the
-// counter until the table is exhausted; every workgroup then exits.
-extern "C" __global__ void __launch_bounds__(256)
+// counter until the table is exhausted; every workgroup then exits.  Two
+// waves per SIMD (registers within 256; every variant's LDS within half a
+// CU): two workgroups per CU.
+extern "C" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 fbcorr_batched(const int4* __restrict__ items, const int nitems, const int4* __restrict__ imgs,
                const float* const* __restrict__ xs, const float* const* __restrict__ wts,
                float* const* __restrict__ ys, int* __restrict__ counter)
@@ -246,19 +249,25 @@ static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const
                 have = parse_config(text, tuned, err);
             }
             if (have && four_waves(tuned) && build_role(d, FBCORR_ROLE_FORWARD, tuned, dev, rb, err) &&
-                rb.main_geom.lds <= dev.lds_per_block / 2) {
+                rb.main_geom.lds <= dev.lds_per_block / 2 - 256) {
                 bv.cfg = tuned;
                 ok = true;
             }
-            // otherwise the heuristic, shrunk until it fits the device
+            // otherwise the heuristic, shrunk until it fits half a CU's LDS
+            // (the launch's occupancy is set by its largest variant: two
+            // workgroups per CU need every variant within half)
             for (int attempt = 0; attempt < 8 && !ok; ++attempt) {
-                ok = build_role(d, FBCORR_ROLE_FORWARD, bv.cfg, dev, rb, err);
+                ok = build_role(d, FBCORR_ROLE_FORWARD, bv.cfg, dev, rb, err) &&
+                     rb.main_geom.lds <= dev.lds_per_block / 2 - 256;
                 if (!ok) {
                     if (bv.cfg.v["kc"] > 4) bv.cfg.v["kc"] /= 2;
                     else if (bv.cfg.v["mr"] > 1) bv.cfg.v["mr"] /= 2;
+                    else if (bv.cfg.v["nt"] > 1) bv.cfg.v["nt"] /= 2;
                     else break;
                 }
             }
+            // the smallest configuration if even that does not fit half
+            if (!ok) ok = build_role(d, FBCORR_ROLE_FORWARD, bv.cfg, dev, rb, err);
             FBC_RETURN_IF(!ok, FBCORR_ERR_UNSUPPORTED, "no batched variant fits for key: " + err);
             const int s = bv.cfg.get("s");
             bv.th = bv.cfg.get("wm") * bv.cfg.get("mt") * bv.cfg.get("mr");

@@ -179,6 +179,21 @@ static void trace_lookup(const char* where, const std::string& key) {
     if (on) fprintf(stderr, "fbcorr cache: %-7s %s\n", where, key.c_str());
 }
 
+// FBCORR_KEEP_SOURCE=<dir> writes every generated source that is compiled
+// (not served from a cache) to <dir>/<key>.hip, with its compiler options in
+// a leading comment, so a kernel can be inspected or rebuilt offline.
+static void keep_source(const KernelSource& ks, const std::string& key) {
+    const char* dir = getenv("FBCORR_KEEP_SOURCE");
+    if (!dir || !*dir) return;
+    FILE* f = fopen((std::string(dir) + "/" + key + ".hip").c_str(), "w");
+    if (!f) return;
+    fputs("// options:", f);
+    for (auto& o : ks.options) fprintf(f, " %s", o.c_str());
+    fputs("\n", f);
+    fwrite(ks.source.data(), 1, ks.source.size(), f);
+    fclose(f);
+}
+
 fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
                              std::shared_ptr<const std::vector<char>>& code) {
     FBC_RETURN_IF(!supported_arch(arch), FBCORR_ERR_UNSUPPORTED, "architecture '" + arch + "' is not supported");
@@ -209,6 +224,7 @@ fbcorr_status compile_cached(const KernelSource& ks, const std::string& arch,
         ++g_misses;
     }
     trace_lookup("compile", key);
+    keep_source(ks, key);
     hiprtcProgram prog;
     hiprtcResult r = hiprtcCreateProgram(&prog, ks.source.c_str(), (ks.file + ".hip").c_str(), 0, nullptr, nullptr);
     FBC_RETURN_IF(r != HIPRTC_SUCCESS, FBCORR_ERR_COMPILE, std::string("hiprtcCreateProgram: ") + hiprtcGetErrorString(r));
