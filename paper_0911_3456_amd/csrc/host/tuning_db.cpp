@@ -8,6 +8,9 @@
 //   <arch> <role> <precision> <batch> <H> <W> <D> <N> <fh> <fw> : <config text>
 //   <arch> nearest u8 <T> <M> <D> : <config text>      (nearest-neighbour search)
 //
+// A batched plan's variants use role "batched" with H = W = 0: one entry per
+// key (fh, fw, D, N), whatever the image sizes.
+//
 // '#' starts a comment.  The file is tuning_db.txt next to libfbcorr.so, or
 // the path in FBCORR_TUNING_DB.  fbcorr_tune can record its winner here.
 #include "plan.h"
