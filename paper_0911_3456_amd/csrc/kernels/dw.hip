@@ -232,9 +232,19 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
 
     // The products of one staged chunk (LDS buffer b).
     auto compute = [&](int b) {
+        // Lane half h walks pixels [h*HS, (h+1)*HS) of the chunk.  When the
+        // chunk has an even number of rows a half starts on a row boundary:
+        // the step's LDS offsets are then a per-lane base plus a constant of
+        // the (unrolled) step, which the reads take as immediate offsets.
+#if (HS % RW) == 0
+        const float* gl = gl_base + b * (PC * GST) + h * (HS * GST);
+        const float* xl = xl_base + b * (XR * XRS) + h * ((HS / RW) * XRS);
+#define STEP_PIXEL(t) (t)
+#else
         const float* gl = gl_base + b * (PC * GST);
         const float* xl = xl_base + b * (XR * XRS);
-        // Lane half h walks pixels [h*HS, (h+1)*HS) of the chunk.
+#define STEP_PIXEL(t) (h * HS + (t))
+#endif
 #if RFULL > 0
 #if UNR == 0
 #pragma unroll
@@ -242,7 +252,7 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
 #pragma unroll UNR
 #endif
         for (int t = 0; t < HS; ++t) {
-            const int p = h * HS + t;
+            const int p = STEP_PIXEL(t);
             const int xo = (p / RW) * XRS + (p % RW) * D;
 #if SAMEROW
             const float a0 = gl[p * GST + arow[0]];
@@ -266,7 +276,7 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
             const int k = RFULL + j;
 #pragma unroll 4
             for (int t = slo[j]; t < shi[j]; ++t) {
-                const int p = h * HS + t;
+                const int p = STEP_PIXEL(t);
                 const int xo = (p / RW) * XRS + (p % RW) * D;
                 const float a = gl[p * GST + arow[k]];
                 const float bb = xl[xo + qoff[k]];
@@ -274,6 +284,7 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
             }
         }
 #endif
+#undef STEP_PIXEL
     };
 
 #if PF == 2
