@@ -349,6 +349,7 @@ static bool geom_dw(const Config& c, const fbcorr_desc& d, const DeviceInfo& di,
     opt(ks.options, "NP", np); opt(ks.options, "GPAD", gpad); opt(ks.options, "XPAD", xpad);
     opt(ks.options, "PF", pf);
     if (bal) opt(ks.options, "BAL", bal);
+    if (c.get("skipe")) opt(ks.options, "SKIPE", 1);
     opt(ks.options, "UNR", unr);
     return true;
 }
@@ -380,7 +381,7 @@ static bool known_keys(const Config& c, std::string& err) {
         {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip",
                    "uunr"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
-        {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr"}},
+        {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }

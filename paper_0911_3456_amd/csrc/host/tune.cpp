@@ -180,6 +180,8 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                         c.v["rh"] = rh; c.v["rw"] = rw; c.v["nw"] = nw;
                                         c.v["tpb"] = (tiles + split - 1) / split;
                                         c.v["np"] = np; c.v["pf"] = pf; c.v["bal"] = bal; c.v["unr"] = unr;
+                                        // round-robin deals: empty last slots skipped
+                                        c.v["skipe"] = bal ? 0 : 1;
                                         grid.push_back(c);
                                     }
             }

@@ -39,6 +39,8 @@
 //                 tiles, see above)
 //            UNR (unrolling of the per-chunk step loop: 0 = complete, which
 //                 turns every LDS address into an immediate offset; k = by k)
+//            SKIPE (1: a wave whose last round-robin slot is empty skips its
+//                 products instead of computing a discarded tile)
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #endif
@@ -74,6 +76,13 @@
 #else
 #define UNR 4
 #endif
+#ifdef FB_SKIPE
+#define SKIPE FB_SKIPE
+#else
+#define SKIPE 0
+#endif
+
+template <int V> struct IConst { static constexpr int value = V; };
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -181,6 +190,9 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
         }
     }
 
+#if SKIPE && !BAL && RFULL > 1
+    const bool last_ok = __builtin_amdgcn_readfirstlane(tval[RFULL - 1] ? 1 : 0) != 0;
+#endif
     f32x16 acc[NSLOT];
 #pragma unroll
     for (int k = 0; k < NSLOT; ++k)
@@ -246,28 +258,39 @@ fbcorr_dw_partial(const float* __restrict__ x, const float* __restrict__ dy,
 #define STEP_PIXEL(t) (h * HS + (t))
 #endif
 #if RFULL > 0
+        // The step loop over the first NS slots (NS a compile-time count).
+        auto steps = [&](auto ns) {
+            constexpr int NS = decltype(ns)::value;
 #if UNR == 0
 #pragma unroll
 #else
 #pragma unroll UNR
 #endif
-        for (int t = 0; t < HS; ++t) {
-            const int p = STEP_PIXEL(t);
-            const int xo = (p / RW) * XRS + (p % RW) * D;
+            for (int t = 0; t < HS; ++t) {
+                const int p = STEP_PIXEL(t);
+                const int xo = (p / RW) * XRS + (p % RW) * D;
 #if SAMEROW
-            const float a0 = gl[p * GST + arow[0]];
+                const float a0 = gl[p * GST + arow[0]];
 #endif
 #pragma unroll
-            for (int k = 0; k < RFULL; ++k) {
+                for (int k = 0; k < NS; ++k) {
 #if SAMEROW
-                const float a = a0;
+                    const float a = a0;
 #else
-                const float a = gl[p * GST + arow[k]];
+                    const float a = gl[p * GST + arow[k]];
 #endif
-                const float bb = xl[xo + qoff[k]];
-                acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
+                    const float bb = xl[xo + qoff[k]];
+                    acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bb, acc[k], 0, 0, 0);
+                }
             }
-        }
+        };
+#if SKIPE && !BAL && RFULL > 1
+        // a wave whose last slot holds no tile skips its products
+        if (last_ok) steps(IConst<RFULL>{});
+        else steps(IConst<RFULL - 1>{});
+#else
+        steps(IConst<RFULL>{});
+#endif
 #endif
 #if BAL
         // This wave's share of the left-over tiles.

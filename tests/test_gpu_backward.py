@@ -103,7 +103,9 @@ BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=
            "rh=1 rw=8 nw=4 tpb=5 np=40 pf=1 bal=1",
            # step loop unrolled completely, or by a factor that leaves a rest
            "rh=2 rw=30 nw=8 tpb=21 np=13 pf=1 unr=0", "rh=1 rw=62 nw=8 tpb=21 np=9 pf=2 bal=1 unr=0",
-           "rh=2 rw=16 nw=4 tpb=14 np=20 pf=0 unr=3"]
+           "rh=2 rw=16 nw=4 tpb=14 np=20 pf=0 unr=3",
+           # waves with an empty last slot skip its products
+           "rh=2 rw=30 nw=8 tpb=21 np=13 pf=1 unr=0 skipe=1", "rh=1 rw=32 nw=4 tpb=14 np=20 pf=2 skipe=1"]
 
 
 @pytest.mark.parametrize("cfg", BX_CFGS)
