@@ -225,6 +225,33 @@ def test_cache_entry_shared_by_kernels_of_one_code_object(tmp_path, monkeypatch)
     nat.cache_clear()
 
 
+def test_kept_sources(tmp_path, monkeypatch):
+    """FBCORR_KEEP_SOURCE keeps every generated source that is compiled, with
+    its options; the batched source keeps each variant's body a function of
+    its own and asks for two waves per SIMD."""
+    import workloads as wl
+    from paper_0911_3456_amd import _native as nat
+    keep = tmp_path / "keep"
+    keep.mkdir()
+    monkeypatch.setenv("FBCORR_CACHE_DIR", str(tmp_path / "cache"))
+    monkeypatch.setenv("FBCORR_KEEP_SOURCE", str(keep))
+    nat.cache_clear()
+    nat.compile_check(nat.make_desc(1, 30, 40, 4, 16, 3, 3), "forward")
+    kept = sorted(keep.glob("igemm-*.hip"))
+    assert len(kept) == 1
+    text = kept[0].read_text()
+    assert text.startswith("// options:") and "-DFB_FH=3" in text.splitlines()[0]
+    assert "igemm_body" in text
+    shapes, _ = wl.draw_batched_list(count=4, seed=32)
+    nat.compile_check_batched([nat.make_desc(1, s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes])
+    (bsrc,) = keep.glob("batched-*.hip")
+    btext = bsrc.read_text()
+    assert "#define FB_BATCHED 1" in btext and "__attribute__((noinline))" in btext
+    assert "amdgpu_waves_per_eu(2)" in btext
+    monkeypatch.delenv("FBCORR_KEEP_SOURCE")
+    nat.cache_clear()
+
+
 def test_tuning_database_supplies_defaults(tmp_path, monkeypatch):
     from paper_0911_3456_amd import cache_clear, codegen, make_desc
     db = tmp_path / "db.txt"
