@@ -205,7 +205,23 @@ def direct_leg(steps: int, warmup: int, xt, wt, s):
             "config": cfg}
 
 
-def precision_leg(steps: int, warmup: int):
+def captured(fn, dev):
+    """fn's launches captured once into a HIP graph (after a warm-up call on
+    a side stream, as graph capture requires)."""
+    import torch
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    return graph
+
+
+def precision_leg(steps: int, warmup: int, use_graph: bool = True):
     import torch
     import workloads as wl
     from paper_0911_3456_amd import Plan
@@ -227,15 +243,25 @@ def precision_leg(steps: int, warmup: int):
         plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, precision=prec, algo=algo, device=dev)
         y = torch.empty(plan.y_shape, device=dev)
         plan.enable_timing(True)
-        t = time_steps(lambda: plan.forward(xt, wt, y), max(3, steps // 5), warmup)
+        t_eager = time_steps(lambda: plan.forward(xt, wt, y), max(3, steps // 5), warmup)
         ms, calls = plan.read_timing()["forward"]
+        plan.enable_timing(False)
         k_ms = ms / max(calls, 1)
-        out["%s_%s" % (prec, algo)] = {"ms": round(t * 1e3, 4), "kernel_ms": round(k_ms, 4),
+        # per call: the whole forward (filter pack for bf16/fp16 and the
+        # correlation) replayed from a HIP graph, as in the step
+        t = t_eager
+        if use_graph:
+            graph = captured(lambda: plan.forward(xt, wt, y), dev)
+            t = time_steps(graph.replay, max(3, steps // 5), warmup)
+            del graph                   # before the plan's kernels are unloaded
+        out["%s_%s" % (prec, algo)] = {"ms": round(t * 1e3, 4), "eager_ms": round(t_eager * 1e3, 4),
+                                        "kernel_ms": round(k_ms, 4),
                                         "tflops": round(s.flops / k_ms / 1e9, 2),
                                         "config": plan.get_config("forward")}
         if (prec, algo) != ("fp32", "igemm"):
             e = (y - y_ref).abs() / a_norm.clamp_min(1e-30)
             out["%s_%s" % (prec, algo)]["err_vs_fp32_matrix"] = {"max": float(e.max()), "mean": float(e.mean())}
+        torch.cuda.synchronize()
         plan.close()
     del y_ref, a_norm
     base = out["fp32_direct"]["ms"]
@@ -580,7 +606,7 @@ def main():
         result["direct_fp32"] = direct_leg(args.steps, args.warmup, xt, wt, s)
     if not args.no_precision and args.only == "step":
         log("precision leg ...")
-        result["precision"] = precision_leg(args.steps, args.warmup)
+        result["precision"] = precision_leg(args.steps, args.warmup, use_graph=not args.no_graph)
     if not args.no_precision and args.only == "step":
         log("differentiation leg ...")
         result["differentiation"] = differentiation_leg(args.steps, args.warmup)

@@ -120,33 +120,55 @@ extern "C" __global__ void __launch_bounds__(256)
 fbcorr_pack_lowp(const float* __restrict__ w, unsigned short* __restrict__ wq,
                  float* __restrict__ unscale)
 {
-    __shared__ float red[256];
+    // One filter per workgroup.  Small filters are read once into registers
+    // (all loads in flight together), larger ones twice; the maximum is
+    // reduced within each wave by shuffles, then across the four waves.
+    constexpr int K = FH * FW * D;
+    constexpr int PER = (K + 255) / 256;
+    constexpr bool HELD = PER <= 32;
+    __shared__ float red[4];
     const int n = blockIdx.x;
-    const int K = FH * FW * D;
     const float* wn = w + (long)n * K;
+    float vals[HELD ? PER : 1];
     float m = 0.f;
-    for (int k = threadIdx.x; k < K; k += 256) m = fmaxf(m, fabsf(wn[k]));
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
+    if (HELD) {
+#pragma unroll
+        for (int i = 0; i < (HELD ? PER : 1); ++i) {
+            const int k = threadIdx.x + i * 256;
+            vals[i] = k < K ? wn[k] : 0.f;
+            m = fmaxf(m, fabsf(vals[i]));
+        }
+    } else {
+        for (int k = threadIdx.x; k < K; k += 256) m = fmaxf(m, fabsf(wn[k]));
     }
-    m = red[0];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
     int ex = 0;
     if (m > 0.f) {
         (void)frexpf(m, &ex);   // m = f * 2^ex, f in [0.5, 1)
         ex -= 1;                // floor(log2 m)
     }
     const float sc = ldexpf(1.0f, -ex);
-    for (int k = threadIdx.x; k < K; k += 256) {
-        const float v = wn[k] * sc;   // exact: power-of-two scale
+    auto put = [&](int k, float x) {
+        const float v = x * sc;       // exact: power-of-two scale
 #if LOWP == 1
         const __bf16 hv = (__bf16)v;
 #else
         const _Float16 hv = (_Float16)v;
 #endif
         wq[(long)n * K + k] = __builtin_bit_cast(unsigned short, hv);
+    };
+    if (HELD) {
+#pragma unroll
+        for (int i = 0; i < (HELD ? PER : 1); ++i) {
+            const int k = threadIdx.x + i * 256;
+            if (k < K) put(k, vals[i]);
+        }
+    } else {
+        for (int k = threadIdx.x; k < K; k += 256) put(k, wn[k]);
     }
     if (threadIdx.x == 0) unscale[n] = ldexpf(1.0f, ex);
 }

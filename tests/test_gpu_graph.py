@@ -61,3 +61,36 @@ def test_captured_step_matches_eager(overlap):
     plan.forward(xt, wt, y)
     plan.backward(xt, wt, gt, dx=dx, dw=dw)
     np.testing.assert_array_equal(host(dw), ref[2])
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_captured_lowp_forward_matches_eager(prec):
+    """The 16-bit forward (filter pack into the workspace, then the
+    correlation) captured and replayed; the filters change between replays
+    so each replay must re-pack them."""
+    need_gpu()
+    import torch
+    from paper_0911_3456_amd import Plan
+    s = wl.Shape(1, 60, 75, 16, 64, 7, 7)
+    x, w, _ = wl.draw_single(s, seed=43)
+    xt, wt = to_dev(x, w)
+    plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, precision=prec)
+    y = torch.empty(plan.y_shape, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.forward(xt, wt, y)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.forward(xt, wt, y)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        wt.mul_(0.5 if rep % 2 else 3.0)          # new filters (new per-filter scales)
+        ref = host(plan.forward(xt, wt))         # eager result for these filters
+        y.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(y), ref, err_msg="replay %d" % rep)
