@@ -249,12 +249,17 @@ def precision_leg(steps: int, warmup: int, use_graph: bool = True):
         k_ms = ms / max(calls, 1)
         # per call: the whole forward (filter pack for bf16/fp16 and the
         # correlation) replayed from a HIP graph, as in the step
-        t = t_eager
+        t, replayed = t_eager, False
         if use_graph:
-            graph = captured(lambda: plan.forward(xt, wt, y), dev)
-            t = time_steps(graph.replay, max(3, steps // 5), warmup)
-            del graph                   # before the plan's kernels are unloaded
+            try:
+                graph = captured(lambda: plan.forward(xt, wt, y), dev)
+                t = time_steps(graph.replay, max(3, steps // 5), warmup)
+                replayed = True
+                del graph               # before the plan's kernels are unloaded
+            except RuntimeError as e:   # reported, and the eager time is used
+                log("precision leg: graph capture failed for %s/%s (%s); eager timing" % (prec, algo, e))
         out["%s_%s" % (prec, algo)] = {"ms": round(t * 1e3, 4), "eager_ms": round(t_eager * 1e3, 4),
+                                        "graph": replayed,
                                         "kernel_ms": round(k_ms, 4),
                                         "tflops": round(s.flops / k_ms / 1e9, 2),
                                         "config": plan.get_config("forward")}
