@@ -155,7 +155,7 @@ bool make_build(const fbnn_desc& d, const Config& c, const DeviceInfo& di, NNBui
     g.ch = (int)std::min<long>(g.ch, g.mts);
     g.nchk = cdiv(g.mts, g.ch);
     if (g.tb * g.nchk >= (1L << 31)) { err = "too many scan workgroups"; return false; }
-    g.norms = LaunchGeom{(int)g.nblk, 1, 256, 0};
+    g.norms = LaunchGeom{(int)cdiv(g.nblk, 4), 1, 256, 0};   // four 64-row blocks per workgroup
     g.offsets = LaunchGeom{1, 1, 1024, 0};
     g.scatter = LaunchGeom{(int)g.nblk, 1, 64, 0};
     g.scan = LaunchGeom{(int)(g.tb * g.nchk), 1, g.wv * 64, 0};

@@ -90,39 +90,59 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 #define HDR_KODD 1
 
 #ifdef FB_NN_NORMS
+// NBW 64-row blocks per workgroup of 256 threads (4 threads per row, one
+// block per pass); every row's loads are issued before any is used.
+#define NBW 4
 extern "C" __global__ void __launch_bounds__(256)
 fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ nn, int* __restrict__ cnt)
 {
-    __shared__ int wsum[4];
-    const long row = (long)blockIdx.x * 64 + (threadIdx.x >> 2);
+    __shared__ int wsum[NBW][4];
     const int q = threadIdx.x & 3;
-    int s = 0;
-    if (row < M) {
+    int s[NBW];
+    long rows[NBW];
 #pragma unroll
-        for (int k = q * 16; k < D; k += 64) {
-            const i32x4 v = *(const i32x4*)(nb + row * D + k);
+    for (int bb = 0; bb < NBW; ++bb) {
+        const long row = ((long)blockIdx.x * NBW + bb) * 64 + (threadIdx.x >> 2);
+        rows[bb] = row;
+        int acc = 0;
+        if (row < M) {
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const unsigned x = (unsigned)v[w];
+            for (int k = q * 16; k < D; k += 64) {
+                const i32x4 v = *(const i32x4*)(nb + row * D + k);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int c = (int)((x >> (8 * j)) & 255u) - 128;
-                    s += c * c;
+                for (int w = 0; w < 4; ++w) {
+                    const unsigned x = (unsigned)v[w];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int c = (int)((x >> (8 * j)) & 255u) - 128;
+                        acc += c * c;
+                    }
                 }
             }
         }
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        s[bb] = acc;
     }
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
+#pragma unroll
+    for (int bb = 0; bb < NBW; ++bb) {
+        const long row = rows[bb];
 #if SPLIT
-    if (q == 0 && row < M) nn[row] = s;
-    const unsigned long long even = __ballot(q == 0 && row < M && (s & 1) == 0);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(even);
-    __syncthreads();
-    if (threadIdx.x == 0) cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (q == 0 && row < M) nn[row] = s[bb];
+        const unsigned long long even = __ballot(q == 0 && row < M && (s[bb] & 1) == 0);
+        if ((threadIdx.x & 63) == 0) wsum[bb][threadIdx.x >> 6] = __popcll(even);
 #else
-    // nn is the start-value array here: -|n|^2, sentinel past the last row
-    if (q == 0 && row < (long)MT * 16) nn[row] = row < M ? -s : NN_PAD_TERM;
+        // nn is the start-value array here: -|n|^2, sentinel past the last row
+        if (q == 0 && row < (long)MT * 16) nn[row] = row < M ? -s[bb] : NN_PAD_TERM;
+#endif
+    }
+#if SPLIT
+    __syncthreads();
+    if (threadIdx.x < NBW) {
+        const long blk = (long)blockIdx.x * NBW + threadIdx.x;
+        if (blk < NB) cnt[blk] = wsum[threadIdx.x][0] + wsum[threadIdx.x][1] + wsum[threadIdx.x][2] + wsum[threadIdx.x][3];
+    }
+#else
     (void)cnt;
     (void)wsum;
 #endif
@@ -131,32 +151,90 @@ fbnn_norms(const unsigned char* __restrict__ nb, int* __restrict__ nn, int* __re
 
 #ifdef FB_NN_OFFSETS
 // One workgroup of 1024 threads; cnt[] becomes the exclusive prefix sum.
+// Each thread owns PER consecutive counts (16-byte loads and stores when PER
+// is a multiple of four); the 1024 segment sums are scanned within each wave
+// by shuffles, then across the 16 waves.
+#define OPER ((NB + 1023) / 1024)
 extern "C" __global__ void __launch_bounds__(1024)
 fbnn_offsets(int* __restrict__ cnt, int* __restrict__ hdr, int* __restrict__ perm, int* __restrict__ cneg)
 {
-    __shared__ int sc[1024];
+    __shared__ int wtot[16];
     __shared__ int tot;
-    const int tid = threadIdx.x;
-    const long per = ((long)NB + 1023) / 1024;
-    const long b0 = tid * per, b1 = (b0 + per < NB) ? b0 + per : NB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long b0 = (long)tid * OPER;
     int s = 0;
-    for (long b = b0; b < b1; ++b) s += cnt[b];
-    sc[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {      // inclusive scan of the segment sums
-        const int v = tid >= off ? sc[tid - off] : 0;
-        __syncthreads();
-        sc[tid] += v;
-        __syncthreads();
+#if OPER > 32
+    // long segments: summed here, read again below
+    for (long b = b0; b < b0 + OPER && b < NB; ++b) s += cnt[b];
+#else
+    int vals[OPER];
+#if OPER % 4 == 0
+#pragma unroll
+    for (int i = 0; i < OPER; i += 4) {
+        i32x4 v = {0, 0, 0, 0};
+        if (b0 + i + 3 < NB) {
+            v = *(const i32x4*)(cnt + b0 + i);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = (b0 + i + j < NB) ? cnt[b0 + i + j] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vals[i + j] = v[j];
     }
-    int run = sc[tid] - s;                          // exclusive start of this segment
-    for (long b = b0; b < b1; ++b) {
+#else
+#pragma unroll
+    for (int i = 0; i < OPER; ++i) vals[i] = (b0 + i < NB) ? cnt[b0 + i] : 0;
+#endif
+#pragma unroll
+    for (int i = 0; i < OPER; ++i) s += vals[i];
+#endif
+    // inclusive scan of the segment sums: within the wave, then the waves
+    int inc = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(inc, off);
+        if (lane >= off) inc += v;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        int t = lane < 16 ? wtot[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int v = __shfl_up(t, off);
+            if (lane >= off) t += v;
+        }
+        if (lane < 16) wtot[lane] = t;
+        if (lane == 15) tot = t;
+    }
+    __syncthreads();
+    int run = inc - s + (wave > 0 ? wtot[wave - 1] : 0);   // exclusive start of this segment
+#if OPER > 32
+    for (long b = b0; b < b0 + OPER && b < NB; ++b) {
         const int v = cnt[b];
         cnt[b] = run;
         run += v;
     }
-    if (tid == 1023) tot = sc[1023];
-    __syncthreads();
+#elif OPER % 4 == 0
+#pragma unroll
+    for (int i = 0; i < OPER; i += 4) {
+        i32x4 v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { v[j] = run; run += vals[i + j]; }
+        if (b0 + i + 3 < NB) {
+            *(i32x4*)(cnt + b0 + i) = v;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) if (b0 + i + j < NB) cnt[b0 + i + j] = v[j];
+        }
+    }
+#else
+#pragma unroll
+    for (int i = 0; i < OPER; ++i) {
+        if (b0 + i < NB) cnt[b0 + i] = run;
+        run += vals[i];
+    }
+#endif
     const int me = tot, mo = M - me;
     const int kodd = (me + 15) / 16;
     if (tid == 0) {
