@@ -59,7 +59,9 @@ def test_lowp_error_bounds(shape, prec):
 LOWP_CFGS = [None, "algo=igemm mf=16 kc=16 s=1 mr=4 mt=2 nt=2 wm=2 wn=1 ks=1",
              "algo=igemm mf=32 kc=8 s=1 mr=2 mt=2 nt=2 wm=2 wn=1 ks=2",
              # 512-pixel workgroup (eight waves of 2x2 tiles)
-             "algo=igemm mf=32 kc=8 s=1 mr=2 mt=2 nt=2 wm=8 wn=1 ks=1 xpad=8 wpad=8"]
+             "algo=igemm mf=32 kc=8 s=1 mr=2 mt=2 nt=2 wm=8 wn=1 ks=1 xpad=8 wpad=8",
+             # whole 16-channel chunks, 32-channel blocks
+             "algo=igemm mf=32 kc=16 s=1 mr=2 mt=2 nt=1 wm=8 wn=1 ks=1 xpad=24 wpad=8"]
 
 
 @pytest.mark.parametrize("cfg", LOWP_CFGS)
