@@ -244,6 +244,10 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad);
     opt(ks.options, "USTAGE", ustage); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
     if (c.get("uunr")) opt(ks.options, "UUNR", 1);
+    if (c.get("swz")) {
+        if (dt == 0 || kc != 16) { err = "igemm: swz needs 16-bit operands and kc=16"; return false; }
+        opt(ks.options, "SWZ", 1);
+    }
     return true;
 }
 
@@ -379,7 +383,7 @@ bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInf
 static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
         {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip",
-                   "uunr"}},
+                   "uunr", "swz"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
     };

@@ -114,6 +114,11 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                         c.v["uunr"] = 1;    // filter rows of a stage unrolled
                                         grid.push_back(c);
                                     }
+                                    if (lp && kc == 16 && (s * kc) % 8 == 0) {
+                                        Config z = c;
+                                        z.v["swz"] = 1;     // swizzled 16-bit tile
+                                        grid.push_back(z);
+                                    }
                                 }
         // a coarse, deterministic subsample of the full grid (Fisher-Yates
         // with a fixed LCG), the default first

@@ -61,7 +61,10 @@ LOWP_CFGS = [None, "algo=igemm mf=16 kc=16 s=1 mr=4 mt=2 nt=2 wm=2 wn=1 ks=1",
              # 512-pixel workgroup (eight waves of 2x2 tiles)
              "algo=igemm mf=32 kc=8 s=1 mr=2 mt=2 nt=2 wm=8 wn=1 ks=1 xpad=8 wpad=8",
              # whole 16-channel chunks, 32-channel blocks
-             "algo=igemm mf=32 kc=16 s=1 mr=2 mt=2 nt=1 wm=8 wn=1 ks=1 xpad=24 wpad=8"]
+             "algo=igemm mf=32 kc=16 s=1 mr=2 mt=2 nt=1 wm=8 wn=1 ks=1 xpad=24 wpad=8",
+             # the same with the swizzled tile, and a 16x16-tile variant of it
+             "algo=igemm mf=32 kc=16 s=1 mr=2 mt=2 nt=1 wm=8 wn=1 ks=1 xpad=24 wpad=8 swz=1",
+             "algo=igemm mf=16 kc=16 s=1 mr=4 mt=2 nt=2 wm=2 wn=1 ks=1 swz=1"]
 
 
 @pytest.mark.parametrize("cfg", LOWP_CFGS)
@@ -75,6 +78,20 @@ def test_lowp_integer_exact(prec, cfg):
     plan = _plan(s, precision=prec)
     if cfg:
         plan.set_config("forward", cfg)
+    y = host(plan.forward(*to_dev(x, w)))
+    np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_swizzled_tile_ragged_channels(prec):
+    """18 input channels: the second 16-channel chunk is mostly zero padding
+    and the tile is staged element by element (the swizzle must be applied
+    on that path too)."""
+    need_gpu()
+    s = wl.Shape(2, 33, 41, 18, 32, 5, 5)
+    x, w, _ = wl.draw_integer(s, seed=78)
+    plan = _plan(s, precision=prec)
+    plan.set_config("forward", "algo=igemm mf=32 kc=16 s=1 mr=2 mt=2 nt=1 wm=8 wn=1 ks=1 xpad=24 wpad=8 swz=1")
     y = host(plan.forward(*to_dev(x, w)))
     np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
 
