@@ -158,3 +158,20 @@ def test_deterministic_repeat():
     a = host(plan.forward(xt, wt))
     b = host(plan.forward(xt, wt))
     np.testing.assert_array_equal(a, b)
+
+
+# the four shapes of the paper's auto-tuning table (input, filter bank)
+PAPER_SHAPES = [wl.Shape(1, 256, 256, 8, 64, 9, 9), wl.Shape(1, 512, 512, 4, 32, 13, 13),
+                wl.Shape(1, 1024, 1024, 8, 16, 5, 5), wl.Shape(1, 2048, 2048, 4, 4, 8, 8)]
+
+
+@pytest.mark.parametrize("algo", ["auto", "direct"])
+@pytest.mark.parametrize("s", PAPER_SHAPES, ids=lambda s: "%dx%dx%d_%dx%dx%d" % (s.H, s.W, s.D, s.N, s.fh, s.fw))
+def test_paper_shapes_shipped_configs_integer_exact(s, algo):
+    """The tuning database's configurations for the paper's four shapes
+    (matrix-core and direct), bit for bit on integer inputs."""
+    need_gpu()
+    x, w, _ = wl.draw_integer(s, seed=17, xmax=2, wmax=2)
+    plan = _plan(s, algo=algo)
+    y = _run(plan, x, w)
+    np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
