@@ -112,6 +112,30 @@ def test_bad_configs_rejected_before_compiling():
     assert e.value.status_name == "FBCORR_ERR_UNSUPPORTED"    # LDS over the device limit
 
 
+def test_kernel_knobs_accepted_and_checked():
+    """The filter-gradient knobs (unr, bal, skipe) and the implicit-GEMM
+    knobs (uunr, swz) reach the generated options; out-of-range values and
+    a swizzle without 16-bit operands are refused before compiling."""
+    from paper_0911_3456_amd import FbcorrError, codegen, make_desc
+    d = make_desc(1, 256, 256, 8, 64, 9, 9)
+    _, o = codegen(d, "backward_w", "algo=dw rh=2 rw=62 nw=8 tpb=21 np=124 unr=0 skipe=1")
+    assert "-DFB_UNR=0" in o and "-DFB_SKIPE=1" in o and "-DFB_BAL" not in o
+    _, o = codegen(d, "backward_w", "algo=dw rh=2 rw=32 nw=8 tpb=25 np=64 bal=1")
+    assert "-DFB_BAL=1" in o
+    _, o = codegen(d, "forward", "algo=igemm kc=8 ustage=3 uunr=1")
+    assert "-DFB_UUNR=1" in o
+    lp = make_desc(1, 128, 128, 16, 64, 7, 7, precision="bf16")
+    _, o = codegen(lp, "forward", "algo=igemm kc=16 mr=2 mt=2 nt=1 wm=8 xpad=24 swz=1")
+    assert "-DFB_SWZ=1" in o
+    for role, cfg in [("backward_w", "algo=dw unr=-1"), ("backward_w", "algo=dw bal=2"),
+                      ("backward_w", "algo=dw nw=2 tpb=42 bal=1"),       # more than 8 slots per wave
+                      ("forward", "algo=igemm kc=8 swz=1")]:           # fp32 operands
+        with pytest.raises(FbcorrError):
+            codegen(d, role, cfg)
+    with pytest.raises(FbcorrError):
+        codegen(lp, "forward", "algo=igemm kc=8 swz=1")                # 8-channel chunks
+
+
 def test_compile_error_is_reported():
     """An injected code-generation failure comes back as FBCORR_ERR_COMPILE
     with the compiler log, and the library stays usable."""
