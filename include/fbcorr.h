@@ -232,10 +232,14 @@ FBCORR_API fbcorr_status fbcorr_plan_set_config(fbcorr_plan_t plan, int role, co
  * backward pass (FBCORR_ERR_UNSUPPORTED). */
 FBCORR_API fbcorr_status fbcorr_plan_set_epilogue(fbcorr_plan_t plan, const char* expr);
 
-/* Kernel timing: when enabled, the library records HIP events around the
- * main kernel of each role on the caller's stream and accumulates the
- * elapsed time when fbcorr_plan_read_timing is called (which synchronises
- * the events).  ms[role] = total milliseconds, calls[role] = launches. */
+/* Kernel timing: when enabled, the library records HIP events around all
+ * the kernels of each role (filter preparation, the main kernel, and for
+ * the filter gradient the fixed-order sum of the partials) on the stream
+ * they are launched on, and accumulates the elapsed time when
+ * fbcorr_plan_read_timing is called (which synchronises the events).
+ * ms[role] = total milliseconds, calls[role] = role executions.  A batched
+ * plan records role 0 around its persistent kernel (eager launches) or its
+ * graph launch. */
 FBCORR_API fbcorr_status fbcorr_plan_enable_timing(fbcorr_plan_t plan, int enable);
 FBCORR_API fbcorr_status fbcorr_plan_read_timing(fbcorr_plan_t plan, double* ms, int64_t* calls, int reset);
 

@@ -26,6 +26,9 @@ struct BVariant {
     Config cfg;
     int th, two, cb;       // tile geometry: output rows, columns, channels
     int lds;
+    // the -DFB_<name>[=<value>] options build_role generated for this key's
+    // standalone kernel (clamped and completed exactly as that kernel was)
+    std::vector<std::string> opts;
 };
 
 struct BatchedState {
@@ -106,23 +109,32 @@ static bool generate(BatchedState& st, const DeviceInfo& di, KernelSource& ks, s
     src << "// Generated persistent batched filter-bank correlation: " << st.vars.size() << " variant(s).\n";
     src << "#define FB_BATCHED 1\n" << header;
     int maxlds = 16;
-    const char* keys[] = {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage"};
-    const char* defs[] = {"FB_MF", "FB_KC", "FB_S", "FB_MR", "FB_MT", "FB_NT", "FB_WM", "FB_WN", "FB_KS",
-                          "FB_XPAD", "FB_WPAD", "FB_USTAGE"};
+    // Options of the standalone kernel that do not apply inside the
+    // persistent kernel: its name, the batch, the image extents (run-time
+    // arguments here) and the workgroup order (set by the dispatch loop).
+    static const std::set<std::string> skip = {"FB_KNAME", "FB_BATCH", "FB_HI", "FB_WI", "FB_HO", "FB_WO",
+                                               "FB_XCDMAP"};
     for (size_t v = 0; v < st.vars.size(); ++v) {
         const BVariant& bv = st.vars[v];
         src << "\n// ---- variant " << v << ": fh=" << bv.fh << " fw=" << bv.fw << " D=" << bv.D << " N=" << bv.N
             << "  [" << bv.cfg.str() << "]\n";
         src << "#undef FB_TAG\n#define FB_TAG v" << v << "\n";
-        src << "#define FB_FH " << bv.fh << "\n#define FB_FW " << bv.fw << "\n#define FB_CIN " << bv.D
-            << "\n#define FB_COUT " << bv.N << "\n#define FB_PADH 0\n#define FB_PADW 0\n#define FB_DT 0\n";
-        for (size_t k = 0; k < sizeof(keys) / sizeof(keys[0]); ++k)
-            src << "#define " << defs[k] << " " << bv.cfg.get(keys[k]) << "\n";
+        // The variant's constants are exactly those its standalone kernel
+        // was built (and tuned) with: clamped values, unrolling switches and
+        // all.
+        std::vector<std::string> defined;
+        for (const std::string& o : bv.opts) {
+            if (o.compare(0, 2, "-D") != 0) continue;
+            const auto eq = o.find('=');
+            const std::string name = o.substr(2, eq == std::string::npos ? std::string::npos : eq - 2);
+            if (skip.count(name) || name.find('(') != std::string::npos) continue;
+            src << "#define " << name << " " << (eq == std::string::npos ? std::string("1") : o.substr(eq + 1))
+                << "\n";
+            defined.push_back(name);
+        }
         src << body << "\n";
         for (auto& m : macros) src << "#undef " << m << "\n";
-        src << "#undef FB_FH\n#undef FB_FW\n#undef FB_CIN\n#undef FB_COUT\n#undef FB_PADH\n#undef FB_PADW\n"
-               "#undef FB_DT\n";
-        for (auto d : defs) src << "#undef " << d << "\n";
+        for (auto& d : defined) src << "#undef " << d << "\n";
         maxlds = std::max(maxlds, bv.lds);
     }
     src << "\n#define MAXLDS " << ((maxlds + 15) / 16 * 16) << "\n";
@@ -275,6 +287,7 @@ static fbcorr_status prepare_batched(const DeviceInfo& dev, int32_t count, const
             bv.two = s * (mf / bv.cfg.get("mr"));
             bv.cb = bv.cfg.get("wn") * bv.cfg.get("nt") * mf / s;
             bv.lds = rb.main_geom.lds;
+            bv.opts = rb.main.options;
             it = keyidx.emplace(key, (int)st->vars.size()).first;
             st->vars.push_back(bv);
         }

@@ -57,7 +57,7 @@ fbcorr_status compile_role(Plan* p, int role, const Config& c) {
     ex.build = rb;
     std::lock_guard<std::mutex> lk(p->mu);
     p->role[role] = std::move(ex);
-    p->have[role] = true;
+    p->have[role].store(true, std::memory_order_release);
     return FBCORR_OK;
 }
 
@@ -82,7 +82,8 @@ fbcorr_status check_ws(void* ws, size_t have, size_t need) {
     return check_ptr(ws, "workspace");
 }
 
-// Timing: events around the main kernel of a role, on the caller's stream.
+// Timing: events around every kernel a role launches (filter preparation,
+// the main kernel and the partial sum), on the stream they are launched on.
 void timing_begin(Plan* p, int role, hipStream_t s, hipEvent_t& a) {
     a = nullptr;
     if (!p->timing) return;
@@ -121,12 +122,14 @@ fbcorr_status run_forward(Plan* p, const RoleExec& ex, const float* x, const flo
     const void* wt = w;
     const float* unscale = nullptr;
     fbcorr_status st;
+    hipEvent_t ev;
+    timing_begin(p, FBCORR_ROLE_FORWARD, s, ev);
     if (!ex.aux.empty() && rb.cfg.algo == "direct") {
         // scalar-weight direct kernel: tap-major copy of the filters
         float* wtt = (float*)ws;
         void* args[] = {(void*)&w, &wtt};
         st = launch(ex.aux[0], rb.aux_geom[0], s, args);
-        if (st != FBCORR_OK) return st;
+        if (st != FBCORR_OK) { timing_end(p, FBCORR_ROLE_FORWARD, s, ev); return st; }
         w = wtt;
     } else if (!ex.aux.empty()) {
         // low precision: scale, round and pack the filters into the workspace
@@ -135,12 +138,10 @@ fbcorr_status run_forward(Plan* p, const RoleExec& ex, const float* x, const flo
         float* us = (float*)(base + rb.ws_unscale);
         void* args[] = {(void*)&w, &wq, &us};
         st = launch(ex.aux[0], rb.aux_geom[0], s, args);
-        if (st != FBCORR_OK) return st;
+        if (st != FBCORR_OK) { timing_end(p, FBCORR_ROLE_FORWARD, s, ev); return st; }
         wt = wq;
         unscale = us;
     }
-    hipEvent_t ev;
-    timing_begin(p, FBCORR_ROLE_FORWARD, s, ev);
     if (rb.cfg.algo == "direct") {
         void* args[] = {(void*)&x, (void*)&w, (void*)&y};
         st = launch(ex.main, rb.main_geom, s, args);
@@ -156,17 +157,17 @@ fbcorr_status run_backward_x(Plan* p, const RoleExec& ex, const float* w, const 
                              hipStream_t s) {
     const RoleBuild& rb = ex.build;
     const float* wfc = w;                   // fused flip: the kernel reads w itself
+    hipEvent_t ev;
+    timing_begin(p, FBCORR_ROLE_BACKWARD_X, s, ev);
     if (!ex.aux.empty()) {
         float* wf = (float*)ws;
         void* a0[] = {(void*)&w, (void*)&wf};
         fbcorr_status st = launch(ex.aux[0], rb.aux_geom[0], s, a0);
-        if (st != FBCORR_OK) return st;
+        if (st != FBCORR_OK) { timing_end(p, FBCORR_ROLE_BACKWARD_X, s, ev); return st; }
         wfc = wf;
     }
     fbcorr_status st;
     const float* unscale = nullptr;
-    hipEvent_t ev;
-    timing_begin(p, FBCORR_ROLE_BACKWARD_X, s, ev);
     void* a1[] = {(void*)&dy, (void*)&wfc, (void*)&unscale, (void*)&dx};
     st = launch(ex.main, rb.main_geom, s, a1);
     timing_end(p, FBCORR_ROLE_BACKWARD_X, s, ev);
@@ -181,11 +182,13 @@ fbcorr_status run_backward_w(Plan* p, const RoleExec& ex, const float* x, const 
     timing_begin(p, FBCORR_ROLE_BACKWARD_W, s, ev);
     void* a0[] = {(void*)&x, (void*)&dy, (void*)&part};
     fbcorr_status st = launch(ex.main, rb.main_geom, s, a0);
+    if (st == FBCORR_OK) {
+        const float* pc = part;
+        void* a1[] = {(void*)&pc, (void*)&dw};
+        st = launch(ex.aux[0], rb.aux_geom[0], s, a1);
+    }
     timing_end(p, FBCORR_ROLE_BACKWARD_W, s, ev);
-    if (st != FBCORR_OK) return st;
-    const float* pc = part;
-    void* a1[] = {(void*)&pc, (void*)&dw};
-    return launch(ex.aux[0], rb.aux_geom[0], s, a1);
+    return st;
 }
 
 size_t backward_ws(const Plan* p, size_t* off_w) {
@@ -196,7 +199,11 @@ size_t backward_ws(const Plan* p, size_t* off_w) {
 }
 
 fbcorr_status ensure_role(Plan* p, int role) {
-    if (p->have[role]) return FBCORR_OK;
+    if (p->have[role].load(std::memory_order_acquire)) return FBCORR_OK;
+    // First use: one thread compiles, the others wait for it and then find
+    // the role installed (an installed role is never replaced from here).
+    std::lock_guard<std::mutex> lk(p->compile_mu);
+    if (p->have[role].load(std::memory_order_acquire)) return FBCORR_OK;
     return compile_role(p, role, default_config(p->desc, role, p->dev));
 }
 

@@ -3,6 +3,8 @@
 
 #include "geometry.h"
 
+#include <atomic>
+
 namespace fbc {
 
 struct RoleExec {
@@ -21,7 +23,12 @@ struct Plan {
     int device = 0;
     DeviceInfo dev;
     RoleExec role[FBCORR_ROLE_COUNT];
-    bool have[FBCORR_ROLE_COUNT] = {false, false, false};
+    // have[r]: role r is compiled and installed.  Set (release) only after
+    // role[r] is complete; the first use of a role compiles it under
+    // compile_mu, and ensure_role never replaces an installed role, so a
+    // caller that saw have[r] may use role[r] while other threads call in.
+    std::atomic<bool> have[FBCORR_ROLE_COUNT] = {{false}, {false}, {false}};
+    std::mutex compile_mu;
     std::mutex mu;
     // kernel timing
     bool timing = false;

@@ -300,3 +300,37 @@ def test_batched_kernel_generation_compiles():
     shapes, _ = wl.draw_batched_list(count=6, seed=9)
     descs = [make_desc(1, s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes]
     assert compile_check_batched(descs) > 0
+
+
+def test_batched_variants_take_the_standalone_constants(tmp_path, monkeypatch):
+    """A batched variant is compiled with exactly the constants of its
+    standalone kernel: a tuned ustage larger than the filter height is
+    clamped (as the standalone kernel's LDS budget assumes) and the unrolled
+    stage loop is kept.  Uses the tuning entries of the GPU test."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import test_gpu_fullsize as tfs
+    from paper_0911_3456_amd import _native as nat
+    db = tmp_path / "db.txt"
+    db.write_text("\n".join(tfs.CLAMP_DB_LINES) + "\n")
+    keep = tmp_path / "keep"
+    keep.mkdir()
+    monkeypatch.setenv("FBCORR_TUNING_DB", str(db))
+    monkeypatch.setenv("FBCORR_CACHE_DIR", str(tmp_path / "cache"))
+    monkeypatch.setenv("FBCORR_KEEP_SOURCE", str(keep))
+    nat.cache_clear()
+    shapes = tfs.CLAMP_SHAPES
+    nat.compile_check_batched([nat.make_desc(1, s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes])
+    (bsrc,) = keep.glob("batched-*.hip")
+    text = bsrc.read_text()
+    parts = text.split("// ---- variant ")[1:]
+    assert len(parts) == 3
+    for part, s in zip(parts, shapes):
+        head = part.splitlines()[0]
+        assert "fh=%d" % s.fh in head and "ustage=3" in head and "uunr=1" in head
+        assert "#define FB_USTAGE %d\n" % min(3, s.fh) in part
+        assert "#define FB_UUNR 1\n" in part
+        assert "#define FB_HI" not in part and "#define FB_KNAME" not in part
+    monkeypatch.delenv("FBCORR_KEEP_SOURCE")
+    monkeypatch.delenv("FBCORR_TUNING_DB")
+    nat.cache_clear()

@@ -210,8 +210,8 @@ def _abs_scale_w(x, g, c, s):
 def test_differentiation_workload():
     """32 inputs 128x128x16, 64 filters 7x7x16, dy ~ N(0,1): GPU gradients
     against windowed FP64 central finite differences at 200 coordinates
-    (100 in x, 100 in w), and against the oracle's gradient on sampled
-    images (dX) and filters (dW)."""
+    (100 in x, 100 in w).  Every element against the oracle's gradient is
+    compared in test_gpu_fullsize.py."""
     need_gpu()
     wk = wl.WORKLOADS["differentiation"]
     s = wk.shape
@@ -229,29 +229,26 @@ def test_differentiation_workload():
     ew = np.max(np.abs(gw - fdw) / aw)
     print("FD: dx %.3e dw %.3e" % (ex, ew))
     assert ex <= TOL and ew <= TOL
-    # oracle gradient on two images (dX) and four filters (dW)
-    for b in (0, s.batch - 1):
-        rx, _ = oracle.backward(x[b:b + 1], w, g[b:b + 1], want_dw=False)
-        sx, _ = oracle.backward(np.abs(x[b:b + 1]), np.abs(w), np.abs(g[b:b + 1]), want_dw=False)
-        assert oracle.normalised_error(dx[b:b + 1], rx, sx)[0] <= TOL
-    for n in (0, 17, 40, s.N - 1):
-        _, rw = oracle.backward(x, w[n:n + 1], g[..., n:n + 1], want_dx=False)
-        _, sw = oracle.backward(np.abs(x), np.abs(w[n:n + 1]), np.abs(g[..., n:n + 1]), want_dx=False)
-        assert oracle.normalised_error(dw[n:n + 1], rw, sw)[0] <= TOL
 
 
 @pytest.mark.parametrize("overlap", [False, True])
 def test_concurrent_backward_from_two_threads(overlap):
     """One plan used from two host threads on two streams with separate
     workspaces (the documented concurrency contract): both results exact,
-    with the gradients in sequence or overlapped on the side stream."""
+    with the gradients in sequence or overlapped on the side stream.  The
+    plan is fresh: both threads' first calls compile the gradient kernels
+    concurrently (one compiles, the other waits and uses that build)."""
     need_gpu()
     import threading
     import torch
     from paper_0911_3456_amd import Plan
     s = wl.Shape(2, 60, 70, 8, 64, 7, 7)
+    # workspace size from a second plan of the same problem, so that the
+    # plan under test has no gradient kernels yet when the threads start
+    sizer = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, overlap_backward=overlap)
+    need = sizer.workspace_size(1)
+    sizer.close()
     plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, overlap_backward=overlap)
-    need = plan.workspace_size(1)
     data, refs, outs = [], [], [None, None]
     for t in range(2):
         x, w, rng = wl.draw_integer(s, seed=50 + t, xmax=3, wmax=3)

@@ -339,3 +339,24 @@ def test_workload_generators():
     assert all(s.H in wl.BATCH_SIDES and s.D in wl.BATCH_DEPTHS and s.N in wl.BATCH_BANKS
                and s.fh in wl.BATCH_FSIZES for s in shapes)
     assert wl.WORKLOADS["fp32"].shape.flops == 2 * 248 * 248 * 64 * 9 * 9 * 8
+
+
+def test_stored_precision_sites_are_the_oracles():
+    """tests/golden/precision_sites.npz (read by the benchmark to state the
+    16-bit error against FP64) holds exactly what the oracle computes at its
+    sites: recomputed here for a few sites, bit for bit."""
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_precision_sites",
+                                                  os.path.join(here, "make_precision_sites.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    data = np.load(os.path.join(here, "precision_sites.npz"))
+    wk = wl.WORKLOADS["precision"]
+    st = mk.sites(wk.shape)
+    np.testing.assert_array_equal(data["sites"], st)
+    x, w, _ = wl.draw_single(wk.shape, wk.seed)
+    pick = [0, 3, 4, len(st) - 1]
+    y, a = mk.compute(x, w, st[pick])
+    np.testing.assert_array_equal(data["y"][pick], y)
+    np.testing.assert_array_equal(data["a"][pick], a)
