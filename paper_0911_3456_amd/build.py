@@ -50,6 +50,18 @@ CHECK_DEFINES = {
                "-DFB_BT=2 -DFB_TG=1 -DFB_XCDMAP=1",
                "-DFB_NN_FINAL -DFB_T=4096 -DFB_M=1048576 -DFB_D=64 -DFB_SPLIT=1 -DFB_FW=4 -DFB_TG=2 -DFB_NCHK=513",
                "-DFB_NN_FINAL -DFB_T=4096 -DFB_M=4096 -DFB_D=64 -DFB_SPLIT=0 -DFB_FW=4 -DFB_TG=1 -DFB_NCHK=128"],
+    "rgemm.hip": ["-DFB_BATCH=1 -DFB_FH=13 -DFB_FW=13 -DFB_CIN=16 -DFB_COUT=128 -DFB_HI=512 -DFB_WI=512 -DFB_HO=500 "
+                  "-DFB_WO=500 -DFB_PADH=0 -DFB_PADW=0 -DFB_DT=1 -DFB_KC=16 -DFB_MR=2 -DFB_MT=4 -DFB_NT=2 -DFB_WM=2 "
+                  "-DFB_WN=2 -DFB_PF=3 -DFB_XPADC=0 -DFB_WPE=2 -DFB_XCDMAP=1 -DFB_KNAME=fbcorr_fwd_rgemm "
+                  "-DFB_EPILOGUE(v,c)=fmaxf(v,0.f)",
+                  "-DFB_BATCH=32 -DFB_FH=7 -DFB_FW=7 -DFB_CIN=16 -DFB_COUT=64 -DFB_HI=128 -DFB_WI=128 -DFB_HO=122 "
+                  "-DFB_WO=122 -DFB_PADH=0 -DFB_PADW=0 -DFB_DT=0 -DFB_KC=16 -DFB_MR=2 -DFB_MT=4 -DFB_NT=2 -DFB_WM=2 "
+                  "-DFB_WN=1 -DFB_PF=3 -DFB_XPADC=0 -DFB_WPE=2 -DFB_XCDMAP=1 -DFB_KNAME=fbcorr_fwd_rgemm",
+                  "-DFB_BATCH=1 -DFB_FH=5 -DFB_FW=5 -DFB_CIN=3 -DFB_COUT=7 -DFB_HI=20 -DFB_WI=19 -DFB_HO=16 "
+                  "-DFB_WO=15 -DFB_PADH=0 -DFB_PADW=0 -DFB_DT=2 -DFB_KC=8 -DFB_MR=1 -DFB_MT=1 -DFB_NT=1 -DFB_WM=1 "
+                  "-DFB_WN=1 -DFB_PF=2 -DFB_XPADC=1 -DFB_WPE=1 -DFB_XCDMAP=0 -DFB_KNAME=fbcorr_fwd_rgemm",
+                  "-DFB_PACK_FRAG -DFB_FH=13 -DFB_FW=13 -DFB_CIN=16 -DFB_COUT=128 -DFB_DT=1 -DFB_KC=16 -DFB_PF=3",
+                  "-DFB_PACK_FRAG -DFB_FH=7 -DFB_FW=7 -DFB_CIN=64 -DFB_COUT=16 -DFB_DT=0 -DFB_KC=16 -DFB_PF=3 -DFB_FLIP"],
     "util.hip": "-DFB_SUM_PARTIALS -DFB_L=41472 -DFB_NP=256 -DFB_RS=16 -DFB_LANES=16 -DFB_FLIP_FILTERS -DFB_N=64 -DFB_FH=9 -DFB_FW=9 -DFB_D=8 "
                 "-DFB_PACK_LOWP -DFB_LOWP=1 -DFB_FILL_INT -DFB_TRANSPOSE_FILTERS -DFB_NPAD=64",
 }
@@ -86,11 +98,21 @@ def build_host() -> str:
     embed_kernels()
     srcs = sorted(glob.glob(os.path.join(HDIR, "*.cpp")))
     tmp = LIB + ".tmp%d" % os.getpid()
-    # Host code only (no device code lives in these files): plain g++ against
-    # the HIP runtime and hiprtc.
+    # The one HIP source of the host library (the allocation-free entry
+    # point's device scratch array): hipcc, device code for gfx950.
+    objdir = os.path.join(CSRC, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for f in sorted(glob.glob(os.path.join(HDIR, "*.hip"))):
+        o = os.path.join(objdir, os.path.basename(f) + ".o")
+        _run([HIPCC, "--offload-arch=" + ARCH, "-O2", "-fPIC", "-std=c++17", "-fvisibility=hidden",
+              *NO_PACKED_FP32, "-I" + INC, "-I" + HDIR, "-c", f, "-o", o])
+        objs.append(o)
+    # Everything else is host code: plain g++ against the HIP runtime and
+    # hiprtc.
     _run(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-Wno-unused-result", "-fvisibility=hidden",
           "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"),
-          "-I" + INC, "-I" + HDIR, *srcs, "-o", tmp,
+          "-I" + INC, "-I" + HDIR, *srcs, *objs, "-o", tmp,
           "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lhiprtc", "-pthread",
           "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, LIB)

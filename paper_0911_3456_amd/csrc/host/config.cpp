@@ -34,7 +34,7 @@ bool parse_config(const std::string& text, Config& base, std::string& err) {
         if (eq == std::string::npos || eq == 0) { err = "bad token '" + tok + "'"; return false; }
         std::string k = tok.substr(0, eq), val = tok.substr(eq + 1);
         if (k == "algo") {
-            if (val != "igemm" && val != "direct" && val != "dw" && val != "nn") {
+            if (val != "igemm" && val != "direct" && val != "dw" && val != "nn" && val != "rgemm") {
                 err = "unknown algo '" + val + "'";
                 return false;
             }
@@ -89,6 +89,31 @@ Config default_igemm(int cin, int cout, bool lowp) {
     c.v = {{"mf", 32}, {"kc", kc}, {"s", s}, {"mr", s >= 2 ? 4 : 1}, {"mt", 1}, {"nt", nt}, {"wm", s >= 2 ? 1 : 4},
            {"wn", 1}, {"ks", s >= 2 ? std::min(4, nchunk) : 1}, {"xpad", lowp ? 8 : 4},
            {"wpad", lowp ? 8 : 4}, {"ustage", 1}, {"xcd", 1}};
+    return c;
+}
+
+// Filter fragments streamed into registers (rgemm.hip): 2 x 2 waves of
+// 4 x 2 tiles (256 pixels x 128 filters per workgroup), whole channel
+// chunks of up to 16 (fp32) or 32 (16-bit) channels, three steps in flight;
+// for at most 16 output channels four waves of eight 16x16 tiles.
+Config default_rgemm(int cin, int cout, bool lowp) {
+    Config c;
+    c.algo = "rgemm";
+    const int pe = lowp ? 8 : 4;
+    int kc = pe;
+    for (int k : {4 * pe, 2 * pe})
+        if (cin % k == 0 || cin > k) { kc = k; break; }
+    if (cin % pe) kc = pe;
+    if (cout <= 16) {
+        // 16x16 tiles: a 32-wide tile would leave half its columns empty
+        c.v = {{"mf", 16}, {"kc", kc}, {"mr", 1}, {"mt", 8}, {"nt", 1}, {"wm", 4}, {"wn", 1}, {"pf", 3},
+               {"xpadc", 0}, {"wpe", 2}, {"xcd", 1}};
+        return c;
+    }
+    const int nt = cout > 32 ? 2 : 1;
+    const int wn = cout > 64 ? 2 : 1;
+    c.v = {{"mf", 32}, {"kc", kc}, {"mr", 2}, {"mt", 4}, {"nt", nt}, {"wm", 2}, {"wn", wn}, {"pf", 3},
+           {"xpadc", 0}, {"wpe", 2}, {"xcd", 1}};
     return c;
 }
 
@@ -251,6 +276,84 @@ static bool geom_igemm(const char* kname, const Config& c, int batch, int hi, in
     return true;
 }
 
+// rgemm: implicit GEMM with the filter fragments streamed into registers
+// (see rgemm.hip).  Returns the packed bank's size in bytes in bank_bytes.
+static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, int wi, int cin, int cout,
+                       int fh, int fw, int padh, int padw, int dt, const DeviceInfo& di, LaunchGeom& g,
+                       KernelSource& ks, KernelSource& pack, LaunchGeom& pack_geom, size_t& bank_bytes,
+                       std::string& err) {
+    const int kc = c.get("kc"), mr = c.get("mr"), mt = c.get("mt"), nt = c.get("nt");
+    const int wm = c.get("wm"), wn = c.get("wn"), pf = c.get("pf"), xpadc = c.get("xpadc");
+    const int wpe = c.v.count("wpe") ? c.get("wpe") : 2, xcd = c.get("xcd"), unr = c.get("unr");
+    const int mf = c.v.count("mf") ? c.get("mf") : 32;
+    if (kc < 1 || mr < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || pf < 1 || xpadc < 0) {
+        err = "rgemm: every knob must be positive"; return false;
+    }
+    if (mf != 32 && mf != 16) { err = "rgemm: mf must be 32 or 16"; return false; }
+    if (pf > 8) { err = "rgemm: pf is at most 8"; return false; }
+    if (wpe < 1 || wpe > 8) { err = "rgemm: wpe must be 1..8"; return false; }
+    if (mf % mr) { err = "rgemm: mr must divide mf"; return false; }
+    const int pe = dt == 0 ? 4 : 8, e = (64 / mf) * pe;
+    const int npl = kc / pe;
+    if (kc % pe || (npl & (npl - 1))) {
+        err = "rgemm: kc must be " + std::to_string(pe) + " times a power of two"; return false;
+    }
+    if (kc > 64) { err = "rgemm: kc is at most 64"; return false; }
+    if (cin % pe && kc != pe) { err = "rgemm: channels not a multiple of the cell width need kc=" + std::to_string(pe); return false; }
+    const int threads = wm * wn * 64;
+    if (threads > std::min(1024, di.max_threads)) { err = "rgemm: too many threads"; return false; }
+    // accumulators, the fragment ring and two sets of A fragments must fit
+    // the per-lane register budget of wpe waves per SIMD (512 / wpe)
+    const int regs = mt * nt * (mf * mf / 64) + pf * nt * 4 + 2 * mt * 4 + 24;
+    if (regs > 512 / wpe) {
+        err = "rgemm: needs about " + std::to_string(regs) + " registers per lane, more than wpe allows"; return false;
+    }
+    const int nstep = (fw * kc + e - 1) / e;
+    const int ntaps = nstep * e / kc;
+    const int nchunk = (cin + kc - 1) / kc;
+    const int ksteps2 = fh * nstep + pf;
+    const int mc = mf / mr;
+    const int th = wm * mt * mr, two = mc, cb = wn * nt * mf;
+    const int tr = th + fh - 1, tc = mc - 1 + ntaps, tcp = tc + xpadc;
+    const long lds = (long)npl * tr * tcp * 16;
+    if (lds > di.lds_per_block) { err = "rgemm: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
+    const int ho = hi + 2 * padh - fh + 1, wo = wi + 2 * padw - fw + 1;
+    const long grid = (long)cdiv(wo, two) * cdiv(ho, th) * cdiv(cout, cb) * batch;
+    if (grid <= 0 || grid > 0x7fffffffL) { err = "rgemm: grid out of range"; return false; }
+    // the packed bank covers whole column blocks of the correlation kernel:
+    // one kilobyte per column tile, chunk and step
+    const int ncols = cdiv(cout, cb) * cb;
+    bank_bytes = (size_t)(ncols / mf) * nchunk * ksteps2 * 1024;
+    g.grid_x = (int)grid;
+    g.grid_y = 1;
+    g.threads = threads;
+    g.lds = (int)lds;
+    ks.name = kname;
+    ks.file = "rgemm";
+    ks.source = template_source("rgemm");
+    ks.options.clear();
+    ks.options.push_back(std::string("-DFB_KNAME=") + kname);
+    opt(ks.options, "BATCH", batch); opt(ks.options, "FH", fh); opt(ks.options, "FW", fw);
+    opt(ks.options, "CIN", cin); opt(ks.options, "COUT", cout);
+    opt(ks.options, "HI", hi); opt(ks.options, "WI", wi); opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
+    opt(ks.options, "PADH", padh); opt(ks.options, "PADW", padw); opt(ks.options, "DT", dt);
+    opt(ks.options, "MF", mf); opt(ks.options, "KC", kc); opt(ks.options, "MR", mr);
+    opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
+    opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "PF", pf);
+    opt(ks.options, "XPADC", xpadc); opt(ks.options, "WPE", wpe); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    if (unr) opt(ks.options, "UNR", 1);
+    pack = KernelSource();
+    pack.name = "fbcorr_pack_frag";
+    pack.file = "rgemm";
+    pack.source = template_source("rgemm");
+    pack.options.push_back("-DFB_PACK_FRAG");
+    opt(pack.options, "FH", fh); opt(pack.options, "FW", fw); opt(pack.options, "CIN", cin);
+    opt(pack.options, "COUT", cout); opt(pack.options, "DT", dt); opt(pack.options, "MF", mf);
+    opt(pack.options, "KC", kc); opt(pack.options, "PF", pf);
+    pack_geom = LaunchGeom{ncols, 1, 256, 0};
+    return true;
+}
+
 static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo& di, LaunchGeom& g,
                         KernelSource& ks, std::string& err) {
     const int th = c.get("th"), tw = c.get("tw"), p = c.get("p"), q = c.get("q"), nb = c.get("nb");
@@ -386,6 +489,7 @@ static bool known_keys(const Config& c, std::string& err) {
                    "uunr", "swz"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
+        {"rgemm", {"mf", "kc", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }
@@ -427,8 +531,24 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
             if (!geom_igemm("fbcorr_fwd_igemm", c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di,
                             rb.main_geom, rb.main, err))
                 return false;
+        } else if (c.algo == "rgemm") {
+            if (c.get("flip")) { err = "flip applies to the input-gradient role only"; return false; }
+            // the filters are always repacked (fragment order; scaled and
+            // rounded for 16-bit operands)
+            KernelSource pk;
+            LaunchGeom pg;
+            size_t bank = 0;
+            if (!geom_rgemm("fbcorr_fwd_rgemm", c, d.batch, d.H, d.W, d.D, d.N, d.fh, d.fw, 0, 0, dt, di,
+                            rb.main_geom, rb.main, pk, pg, bank, err))
+                return false;
+            rb.aux.push_back(pk);
+            rb.aux_geom.push_back(pg);
+            rb.ws_lowp_w = 0;
+            rb.ws_unscale = align256(bank);
+            rb.ws_bytes = rb.ws_unscale + align256((size_t)pg.grid_x * 4);
+            return true;
         } else {
-            err = "forward role needs algo=igemm or algo=direct";
+            err = "forward role needs algo=igemm, algo=rgemm or algo=direct";
             return false;
         }
         if (dt != 0) {
@@ -443,8 +563,24 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
         }
         return true;
     }
+    if (role == FBCORR_ROLE_BACKWARD_X && c.algo == "rgemm") {
+        // dx = valid correlation of dy (padded by fh-1, fw-1) with the
+        // flipped, transposed filters, which the pack reads straight from
+        // the forward bank (the flip is part of the repacking)
+        KernelSource pk;
+        LaunchGeom pg;
+        size_t bank = 0;
+        if (!geom_rgemm("fbcorr_dx_rgemm", c, d.batch, ho, wo, d.N, d.D, d.fh, d.fw, d.fh - 1, d.fw - 1, 0, di,
+                        rb.main_geom, rb.main, pk, pg, bank, err))
+            return false;
+        pk.options.push_back("-DFB_FLIP");
+        rb.aux.push_back(pk);
+        rb.aux_geom.push_back(pg);
+        rb.ws_bytes = align256(bank);
+        return true;
+    }
     if (role == FBCORR_ROLE_BACKWARD_X) {
-        if (c.algo != "igemm") { err = "input-gradient role needs algo=igemm"; return false; }
+        if (c.algo != "igemm") { err = "input-gradient role needs algo=igemm or algo=rgemm"; return false; }
         // dx = valid correlation of dy (padded by fh-1, fw-1) with flipped,
         // transposed filters: CIN = N, COUT = D, input extent Ho x Wo.
         if (!geom_igemm("fbcorr_dx_igemm", c, d.batch, ho, wo, d.N, d.D, d.fh, d.fw, d.fh - 1, d.fw - 1, 0, di,
@@ -493,16 +629,44 @@ Config default_config(const fbcorr_desc& d, int role, const DeviceInfo& di) {
         probe.algo = c.algo;
         if (parse_config(text, probe, err)) {
             // start from the chosen algorithm's heuristic and apply the entry
+            const int cin = role == FBCORR_ROLE_BACKWARD_X ? d.N : d.D;
+            const int cout = role == FBCORR_ROLE_BACKWARD_X ? d.D : d.N;
+            const bool lp = d.precision != FBCORR_FP32 && role == FBCORR_ROLE_FORWARD;
             Config base = probe.algo == c.algo ? c
                           : (probe.algo == "direct" ? default_direct(d)
-                                                    : default_igemm(role == FBCORR_ROLE_BACKWARD_X ? d.N : d.D,
-                                                                    role == FBCORR_ROLE_BACKWARD_X ? d.D : d.N,
-                                                                    d.precision != FBCORR_FP32));
+                             : probe.algo == "rgemm" ? default_rgemm(cin, cout, lp)
+                                                     : default_igemm(cin, cout, d.precision != FBCORR_FP32));
             RoleBuild rb;
             if (parse_config(text, base, err) && build_role(d, role, base, di, rb, err)) return base;
         }
     }
     return heuristic_default(d, role, di);
+}
+
+bool config_from_text(const fbcorr_desc& d, int role, const DeviceInfo& di, const std::string& text,
+                      bool reset_named, Config& out, std::string& err) {
+    // A text that names another algorithm than the role's default starts
+    // from that algorithm's hand-written defaults ("algo=direct" alone is a
+    // complete configuration); with reset_named a forward-role text that
+    // names an algorithm always does.  Otherwise unnamed knobs keep the
+    // role's default.
+    Config c = default_config(d, role, di);
+    const int cin = role == FBCORR_ROLE_BACKWARD_X ? d.N : d.D;
+    const int cout = role == FBCORR_ROLE_BACKWARD_X ? d.D : d.N;
+    const bool lp = d.precision != FBCORR_FP32 && role == FBCORR_ROLE_FORWARD;
+    if (role == FBCORR_ROLE_FORWARD) {
+        if (text.find("algo=direct") != std::string::npos) c = default_direct(d);
+        if (text.find("algo=igemm") != std::string::npos && (reset_named || c.algo != "igemm"))
+            c = default_igemm(cin, cout, lp);
+        if (text.find("algo=rgemm") != std::string::npos && (reset_named || c.algo != "rgemm"))
+            c = default_rgemm(cin, cout, lp);
+    } else if (role == FBCORR_ROLE_BACKWARD_X) {
+        if (text.find("algo=igemm") != std::string::npos && c.algo != "igemm") c = default_igemm(cin, cout, false);
+        if (text.find("algo=rgemm") != std::string::npos && c.algo != "rgemm") c = default_rgemm(cin, cout, false);
+    }
+    if (!parse_config(text, c, err)) return false;
+    out = c;
+    return true;
 }
 
 Config heuristic_default(const fbcorr_desc& d, int role, const DeviceInfo& di) {

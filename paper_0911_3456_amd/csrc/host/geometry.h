@@ -40,7 +40,14 @@ void tuning_db_reload();
 bool tuning_db_lookup_key(const std::string& key, std::string& cfg);
 bool tuning_db_record_key(const std::string& key, const std::string& cfg, std::string& err);
 Config default_igemm(int cin, int cout, bool lowp);
+Config default_rgemm(int cin, int cout, bool lowp);
 Config default_direct(const fbcorr_desc& d);
+// The configuration a text such as "algo=rgemm mt=2" describes for a role:
+// unnamed knobs come from the role's default, or from the named algorithm's
+// hand-written defaults when it differs from the default's (always, on the
+// forward role, with reset_named).
+bool config_from_text(const fbcorr_desc& d, int role, const DeviceInfo& di, const std::string& text,
+                      bool reset_named, Config& out, std::string& err);
 bool build_role(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,
                 RoleBuild& rb, std::string& err);
 

@@ -160,8 +160,11 @@ fbcorr_status run_backward_x(Plan* p, const RoleExec& ex, const float* w, const 
     hipEvent_t ev;
     timing_begin(p, FBCORR_ROLE_BACKWARD_X, s, ev);
     if (!ex.aux.empty()) {
+        // flipped copy of the filters (fbcorr_flip_filters), or the
+        // fragment-ordered flipped bank (fbcorr_pack_frag, no scales)
         float* wf = (float*)ws;
-        void* a0[] = {(void*)&w, (void*)&wf};
+        float* no_scale = nullptr;
+        void* a0[] = {(void*)&w, (void*)&wf, (void*)&no_scale};
         fbcorr_status st = launch(ex.aux[0], rb.aux_geom[0], s, a0);
         if (st != FBCORR_OK) { timing_end(p, FBCORR_ROLE_BACKWARD_X, s, ev); return st; }
         wfc = wf;
@@ -405,13 +408,9 @@ fbcorr_status fbcorr_plan_set_config(fbcorr_plan_t plan, int role, const char* c
     FBC_RETURN_IF(p->batched, FBCORR_ERR_UNSUPPORTED, "batched plans are configured at plan time");
     FBC_RETURN_IF(role < 0 || role >= FBCORR_ROLE_COUNT, FBCORR_ERR_INVALID_ARGUMENT, "unknown role");
     DeviceGuard g(p->device);
-    Config c = default_config(p->desc, role, p->dev);
-    // "algo=direct" alone selects that algorithm's defaults
-    std::string text(cfg), err;
-    if (text.find("algo=direct") != std::string::npos && role == FBCORR_ROLE_FORWARD) c = default_direct(p->desc);
-    if (text.find("algo=igemm") != std::string::npos && role == FBCORR_ROLE_FORWARD)
-        c = default_igemm(p->desc.D, p->desc.N, p->desc.precision != FBCORR_FP32);
-    if (!parse_config(text, c, err)) {
+    Config c;
+    std::string err;
+    if (!config_from_text(p->desc, role, p->dev, cfg, true, c, err)) {
         set_error(FBCORR_ERR_INVALID_ARGUMENT, err);
         return FBCORR_ERR_INVALID_ARGUMENT;
     }
@@ -497,9 +496,7 @@ static fbcorr_status offline_build(const fbcorr_desc* desc, int role, const char
     Config c = default_config(*desc, role, di);
     std::string err;
     if (cfg) {
-        std::string text(cfg);
-        if (text.find("algo=direct") != std::string::npos && role == FBCORR_ROLE_FORWARD) c = default_direct(*desc);
-        if (!parse_config(text, c, err)) {
+        if (!config_from_text(*desc, role, di, cfg, false, c, err)) {
             set_error(FBCORR_ERR_INVALID_ARGUMENT, err);
             return FBCORR_ERR_INVALID_ARGUMENT;
         }

@@ -42,6 +42,18 @@ static TuneLayout tune_layout(const Plan* p) {
     // largest role workspace any candidate may ask for
     size_t rw = std::max(align256(t.nw * 2) + align256((size_t)d.N * 4), align256(t.nw * 4));
     rw = std::max(rw, align256(kMaxPartialsForTuning * t.nw * 4));
+    // the fragment-ordered bank of the register-streamed forward kernel:
+    // columns padded to at most 256, chunks of at least 4 channels, steps of
+    // at least 8 values (one padded step per filter row and chunk) and 8
+    // ring steps per chunk, at most 64 bytes per column and step
+    // (forward: columns N over D channels; input gradient: D over N)
+    for (int r = 0; r < 2; ++r) {
+        const int co = r == 0 ? d.N : d.D, ci = r == 0 ? d.D : d.N;
+        const size_t cols = (size_t)(co + 255) / 256 * 256;
+        const size_t chunks = (size_t)(ci + 3) / 4;
+        const size_t steps = (size_t)d.fh * d.fw * (ci + 63) / 8 + chunks * d.fh + chunks * 8;
+        rw = std::max(rw, align256(cols * steps * 64) + align256(cols * 4));
+    }
     off += rw;
     t.total = off;
     return t;
@@ -127,8 +139,48 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
             st = st * 6364136223846793005ull + 1442695040888963407ull;
             std::swap(grid[i - 1], grid[(st >> 33) % i]);
         }
+        // Filter fragments streamed into registers: tile size, chunk width,
+        // tile rows, per-wave tiles and waves, ring depth, row padding,
+        // register budget.  Interleaved with the staged-filter
+        // grid so that any candidate budget samples both.
+        std::vector<Config> rgrid;
+        {
+            const Config rb = default_rgemm(cin, cout, lp);
+            const int pe = lp ? 8 : 4;
+            std::vector<int> rkcs = {pe};
+            for (int k : {2 * pe, 4 * pe, 8 * pe})
+                if (k <= std::max(cin, 2 * pe) && (cin % pe == 0)) rkcs.push_back(k);
+            const int rshapes[][4] = {{4, 2, 2, 2}, {4, 2, 1, 2}, {4, 2, 4, 1}, {2, 2, 2, 2}, {2, 2, 4, 2},
+                                      {4, 1, 2, 4}, {4, 1, 4, 2}, {8, 1, 2, 2}, {2, 4, 2, 1}, {4, 2, 2, 1},
+                                      {2, 2, 4, 1}, {4, 1, 4, 1}, {4, 4, 1, 2}, {2, 1, 4, 2}, {8, 1, 1, 4}};
+            for (int kc : rkcs)
+              for (int mf : {32, 16})
+                for (int mr : {1, 2, 4})
+                    for (auto& sh : rshapes)
+                        for (int pf : {2, 3, 4, 6})
+                            for (int xp : {0, 1})
+                                for (int wpe : {1, 2}) {
+                                    Config c = rb;
+                                    if (sh[1] * sh[3] * mf > std::max(mf, ((cout + mf - 1) / mf) * mf)) continue;
+                                    if (mf == 16 && cout > 64) continue;
+                                    c.v["mf"] = mf;
+                                    c.v["kc"] = kc; c.v["mr"] = mr;
+                                    c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
+                                    c.v["pf"] = pf; c.v["xpadc"] = xp; c.v["wpe"] = wpe;
+                                    rgrid.push_back(c);
+                                }
+            uint64_t st2 = 0xD1B54A32D192ED03ull;
+            for (size_t i = rgrid.size(); i > 1; --i) {
+                st2 = st2 * 6364136223846793005ull + 1442695040888963407ull;
+                std::swap(rgrid[i - 1], rgrid[(st2 >> 33) % i]);
+            }
+        }
         add(out, seen, base);
-        for (auto& c : grid) add(out, seen, c);
+        if (!rgrid.empty()) add(out, seen, default_rgemm(cin, cout, lp));
+        for (size_t i = 0; i < std::max(grid.size(), rgrid.size()); ++i) {
+            if (i < rgrid.size()) add(out, seen, rgrid[i]);
+            if (i < grid.size()) add(out, seen, grid[i]);
+        }
         if (direct_only) out.clear();
         if ((with_direct || direct_only) && role == FBCORR_ROLE_FORWARD && !lowp) {
             const Config db = default_direct(d);

@@ -1,0 +1,455 @@
+// Implicit-GEMM valid correlation on the matrix cores with the filter
+// operand streamed straight into registers.
+//
+//   O[b,i,j,c] = sum_{u<FH, v<FW, k<CIN} Ipad[b, i+u, j+v, k] * Wt[c, u, v, k]
+//
+// (Ipad: the input I[b][HI][WI][CIN] with PADH/PADW rows/columns of virtual
+// zeros on every side.)  Same GEMM view as the LDS-staged kernel: rows =
+// output pixels, columns = output channels (filters), contraction over
+// (u, v, k).  What differs is where the operands come from.
+//
+// * The filter bank is first rewritten by fbcorr_pack_frag (below) in the
+//   exact order in which the matrix-core instructions consume it: for an
+//   MF-filter column tile j, a channel chunk, a filter row u and a step t,
+//   the 64 lanes' 16-byte fragments are one contiguous kilobyte.  Each wave
+//   loads its own column tiles' fragments from L2 with one 16-byte load per
+//   lane per tile and step, PF steps ahead, into a ring of registers.  The
+//   filters never pass through LDS, so there is no per-filter-row staging
+//   and no barrier inside a channel chunk: a chunk is one uninterrupted run
+//   of FH * NSTEP steps of products.
+// * The input tile of a channel chunk (with its FH-1 / FW-1 halo) is staged
+//   once in LDS as 16-byte cells of PE consecutive channels, NPL = KC/PE
+//   planes of cells.  The 16 lanes that read together take 16 consecutive
+//   pixel columns of one plane: 256 contiguous bytes, free of bank
+//   conflicts for any row stride.
+//
+// Contraction order.  Within a filter row u and chunk, the run of (v, k)
+// pairs (tap-major, FW*KC values, zero-padded to NSTEP*E) is cut into steps
+// of E = NKG*PE values, NKG = 64/MF lane groups; lane group g of an
+// instruction takes values [E*t + g*PE, E*t + g*PE + PE) of step t.  Run
+// position e lies in cell plane (e % KC)/PE, tap e / KC.  For 16-bit
+// operands one step is one v_mfma_f32_{32x32x16,16x16x32} (8 values per
+// lane); for fp32 it is four v_mfma_f32_{32x32x2,16x16x4}_f32 (value q of the
+// lane's cell in product q).  A and B use the same order, so every padding
+// value multiplies a zero weight.
+//
+// Compile-time constants (FB_<name>):
+//   problem  BATCH FH FW CIN COUT HI WI HO WO PADH PADW
+//   DT       0 fp32 operands, 1 bf16, 2 fp16 (B pre-scaled and rounded by
+//            the pack; UNSCALE[c] multiplies each output)
+//   tiling   MF (32 or 16: MFMA tile), KC (channels per chunk: PE times a
+//            power of two), MR (rows of an MF-pixel tile), MT NT (tiles per
+//            wave), WM WN (waves), PF (filter-fragment ring depth in steps),
+//            XPADC (LDS row padding in cells), WPE (waves per SIMD the
+//            register budget is sized for), UNR (1: unroll the step loop
+//            completely), XCDMAP (XCD-aware workgroup order)
+//   naming   KNAME   EPILOGUE(v, c) as in the LDS-staged kernel
+#ifndef __HIPCC_RTC__
+#include <hip/hip_runtime.h>
+#endif
+
+#ifdef FB_INJECT_ERROR
+#error "injected code-generation failure (test hook)"
+#endif
+
+typedef float rg_f32x4 __attribute__((ext_vector_type(4)));
+typedef float rg_f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int rg_u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 rg_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 rg_f16x8 __attribute__((ext_vector_type(8)));
+
+#define FH FB_FH
+#define FW FB_FW
+#define CIN FB_CIN
+#define COUT FB_COUT
+#define DT FB_DT
+#define KC FB_KC
+#ifdef FB_MF
+#define MF FB_MF
+#else
+#define MF 32
+#endif
+
+#if DT == 0
+#define PE 4                      // channels per 16-byte cell
+#else
+#define PE 8
+#endif
+#define NKG (64 / MF)             // lane groups of one instruction
+#define E (NKG * PE)              // contraction values per step
+#define NPL (KC / PE)             // cell planes per channel chunk
+#define NSTEP ((FW * KC + E - 1) / E)   // steps per filter row and chunk
+#define NTAPS ((NSTEP * E) / KC)        // taps covered, padding included
+#define NCHUNK ((CIN + KC - 1) / KC)
+#define KSTEPS (FH * NSTEP)             // steps per chunk
+#ifdef FB_PF
+#define KSTEPS2 (KSTEPS + FB_PF)        // packed steps per chunk: PF zero steps after the real ones
+#endif
+
+static_assert(MF == 32 || MF == 16, "MFMA tiles are 32x32 or 16x16");
+static_assert(KC % PE == 0 && ((KC / PE) & (KC / PE - 1)) == 0, "KC must be PE times a power of two");
+
+// Cell offset (plane * plane_cells + tap) of run position e.
+#define RUN_PLANE(e) (((e) % KC) / PE)
+#define RUN_TAP(e) ((e) / KC)
+
+// ------------------------------------------------------------------ pack
+#ifdef FB_PACK_FRAG
+// One workgroup per column c of the packed bank (whole column blocks of the
+// correlation kernel; columns at or past COUT are zero).  Layout: 16-byte
+// cell ((j*NCHUNK + chunk)*KSTEPS2 + u*NSTEP + t)*64 + lane for column tile
+// j = c / MF, lane = MF*g + c%MF.  16-bit operands: e_c = floor(log2
+// max|w[c]|), values scaled by 2^-e_c (exact) and rounded to nearest even,
+// unscale[c] = 2^e_c (an all-zero filter gets e_c = 0).  FB_FLIP: the
+// filters are those of the input-gradient correlation, read from the
+// forward bank w[CIN][FH][FW][COUT] flipped in (u, v) with the channel axes
+// exchanged.
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* __restrict__ unscale)
+{
+    constexpr int K = FH * FW * CIN;
+    const int c = blockIdx.x;
+    const int j = c / MF, col = c % MF;
+    const bool real = c < COUT;
+    auto src = [&](int u, int v, int ch) -> float {
+#ifdef FB_FLIP
+        return w[(((long)ch * FH + (FH - 1 - u)) * FW + (FW - 1 - v)) * COUT + c];
+#else
+        return w[(((long)c * FH + u) * FW + v) * CIN + ch];
+#endif
+    };
+    float sc = 1.0f;
+#if DT != 0
+    __shared__ float red[4];
+    float m = 0.f;
+    if (real)
+        for (int k = threadIdx.x; k < K; k += 256) {
+            const int ch = k % CIN, v = (k / CIN) % FW, u = k / (CIN * FW);
+            m = fmaxf(m, fabsf(src(u, v, ch)));
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int ex = 0;
+    if (m > 0.f) {
+        (void)frexpf(m, &ex);     // m = f * 2^ex, f in [0.5, 1)
+        ex -= 1;                  // floor(log2 m)
+    }
+    sc = ldexpf(1.0f, -ex);
+    if (threadIdx.x == 0) unscale[c] = real ? ldexpf(1.0f, ex) : 0.f;
+#else
+    (void)unscale;
+#endif
+    // items: (chunk, filter row, tap slot, plane), plane fastest
+    constexpr int ITEMS = NCHUNK * FH * NTAPS * NPL;
+    for (int e = threadIdx.x; e < ITEMS; e += 256) {
+        const int p = e % NPL;
+        int r = e / NPL;
+        const int vv = r % NTAPS;
+        r /= NTAPS;
+        const int u = r % FH, kci = r / FH;
+        const int el = vv * KC + p * PE;          // position in the row's run
+        const int t = el / E, g = (el % E) / PE;
+        float vals[PE];
+#pragma unroll
+        for (int i = 0; i < PE; ++i) {
+            const int ch = kci * KC + p * PE + i;
+            vals[i] = (real && vv < FW && ch < CIN) ? src(u, vv, ch) * sc : 0.f;
+        }
+        rg_u32x4 cell;
+#if DT == 0
+        cell = __builtin_bit_cast(rg_u32x4, (rg_f32x4){vals[0], vals[1], vals[2], vals[3]});
+#else
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#if DT == 1
+            const unsigned lo = __builtin_bit_cast(unsigned short, (__bf16)vals[2 * i]);
+            const unsigned hi = __builtin_bit_cast(unsigned short, (__bf16)vals[2 * i + 1]);
+#else
+            const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)vals[2 * i]);
+            const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)vals[2 * i + 1]);
+#endif
+            cell[i] = lo | (hi << 16);
+        }
+#endif
+        bp[(((long)j * NCHUNK + kci) * KSTEPS2 + u * NSTEP + t) * 64 + g * MF + col] = cell;
+    }
+    // the zero steps after each chunk (read by the ring's last refills)
+    for (int e = threadIdx.x; e < NCHUNK * (KSTEPS2 - KSTEPS) * NKG; e += 256) {
+        const int g = e % NKG, st = (e / NKG) % (KSTEPS2 - KSTEPS), kci = e / (NKG * (KSTEPS2 - KSTEPS));
+        const rg_u32x4 z = {0u, 0u, 0u, 0u};
+        bp[(((long)j * NCHUNK + kci) * KSTEPS2 + KSTEPS + st) * 64 + g * MF + col] = z;
+    }
+}
+#endif  // FB_PACK_FRAG
+
+// ---------------------------------------------------------------- correlation
+#ifndef FB_PACK_FRAG
+#define BATCH FB_BATCH
+#define HI FB_HI
+#define WI FB_WI
+#define HO FB_HO
+#define WO FB_WO
+#define PADH FB_PADH
+#define PADW FB_PADW
+#define MR FB_MR
+#define MT FB_MT
+#define NT FB_NT
+#define WM FB_WM
+#define WN FB_WN
+#define PF FB_PF
+#define XPADC FB_XPADC
+#ifdef FB_WPE
+#define WPE FB_WPE
+#else
+#define WPE 2
+#endif
+
+#define NREG (MF * MF / 64)           // accumulator registers per tile
+#define MC (MF / MR)                  // pixel columns of a tile
+#define TH (WM * MT * MR)             // output rows per workgroup
+#define TWO MC                        // output columns per workgroup
+#define CB (WN * NT * MF)             // filters per workgroup
+#define TR (TH + FH - 1)              // tile rows
+#define TC (MC - 1 + NTAPS)           // tile columns any lane reads
+#define TCP (TC + XPADC)              // tile row stride in cells
+#define PLANE (TR * TCP)              // cells per plane
+#define TILE_CELLS (NPL * PLANE)
+#define NTHREADS (WM * WN * 64)
+
+static_assert(MF % MR == 0, "MR must divide MF");
+static_assert(PF >= 1, "ring depth");
+static_assert(CIN % PE == 0 || KC == PE, "partial cells need KC == PE");
+
+#if MF == 32
+typedef rg_f32x16 rg_acc;
+#else
+typedef rg_f32x4 rg_acc;
+#endif
+
+__device__ __forceinline__ rg_u32x4 rg_cell(const float* v) {
+    rg_u32x4 c;
+#if DT == 0
+    c = __builtin_bit_cast(rg_u32x4, (rg_f32x4){v[0], v[1], v[2], v[3]});
+#else
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#if DT == 1
+        const unsigned lo = __builtin_bit_cast(unsigned short, (__bf16)v[2 * i]);      // nearest even
+        const unsigned hi = __builtin_bit_cast(unsigned short, (__bf16)v[2 * i + 1]);
+#else
+        const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)v[2 * i]);
+        const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)v[2 * i + 1]);
+#endif
+        c[i] = lo | (hi << 16);
+    }
+#endif
+    return c;
+}
+
+// acc += A * B for one step of one (pixel tile, column tile) pair.
+__device__ __forceinline__ void rg_mma(rg_acc& acc, const rg_u32x4 a, const rg_u32x4 b) {
+#if DT == 0
+    const rg_f32x4 af = __builtin_bit_cast(rg_f32x4, a);
+    const rg_f32x4 bf = __builtin_bit_cast(rg_f32x4, b);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#if MF == 32
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bf[q], acc, 0, 0, 0);
+#else
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[q], bf[q], acc, 0, 0, 0);
+#endif
+    }
+#elif DT == 1 && MF == 32
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(rg_bf16x8, a), __builtin_bit_cast(rg_bf16x8, b),
+                                                  acc, 0, 0, 0);
+#elif DT == 1
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(rg_bf16x8, a), __builtin_bit_cast(rg_bf16x8, b),
+                                                  acc, 0, 0, 0);
+#elif MF == 32
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(rg_f16x8, a), __builtin_bit_cast(rg_f16x8, b),
+                                                 acc, 0, 0, 0);
+#else
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(rg_f16x8, a), __builtin_bit_cast(rg_f16x8, b),
+                                                 acc, 0, 0, 0);
+#endif
+}
+
+extern "C" __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const float* __restrict__ UNSCALE,
+         float* __restrict__ O)
+{
+    __shared__ rg_u32x4 tile[TILE_CELLS];
+
+    // Workgroup -> (image, column block, tile row, tile column); with XCDMAP
+    // each XCD gets a contiguous range (shared halos stay in its L2).
+    const int ntx = (WO + TWO - 1) / TWO;
+    const int nty = (HO + TH - 1) / TH;
+    const int ncb = (COUT + CB - 1) / CB;
+    const int total = ntx * nty * ncb * BATCH;
+    int lin = blockIdx.x;
+#if FB_XCDMAP
+    {
+        const int q = total / 8, r = total % 8, x = lin % 8;
+        lin = x * q + (x < r ? x : r) + lin / 8;
+    }
+#endif
+    const int tx = lin % ntx;
+    const int ty = (lin / ntx) % nty;
+    const int cblk = (lin / (ntx * nty)) % ncb;
+    const int b = lin / (ntx * nty * ncb);
+    const int oi0 = ty * TH, oj0 = tx * TWO, c0 = cblk * CB;
+    const float* Ib = I + (long)b * HI * WI * CIN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int lr = lane % MF, g = lane / MF;       // tile row (pixel) / lane group
+    const int ti = lr / MC, tj = lr % MC;
+    // this lane's first cell (step 0, filter row 0, pixel tile 0)
+    const int lb = RUN_PLANE(g * PE) * PLANE + (wm * MT * MR + ti) * TCP + tj + RUN_TAP(g * PE);
+    // this wave's first column tile; column tiles are NCHUNK*KSTEPS2
+    // kilobyte blocks apart (the packed bank has whole column blocks, so
+    // every tile a wave names exists)
+    const int j0 = c0 / MF + wn * NT;
+    const rg_u32x4* bw = Bp + (long)j0 * NCHUNK * KSTEPS2 * 64 + lane;
+
+    rg_acc acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < NREG; ++r) acc[mt][nt][r] = 0.f;
+
+#pragma unroll 1
+    for (int kci = 0; kci < NCHUNK; ++kci) {
+        const rg_u32x4* bc = bw + (long)kci * KSTEPS2 * 64;
+        rg_u32x4 bq[PF][NT];
+        // the first PF steps' fragments are in flight while the tile is staged
+#pragma unroll
+        for (int r = 0; r < PF; ++r)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                bq[r][nt] = bc[((long)nt * NCHUNK * KSTEPS2 + r) * 64];
+        if (kci > 0) __syncthreads();        // every wave is done with the previous chunk
+        // Stage the chunk's input tile: cell (plane p, row r, column cc) =
+        // channels kci*KC + p*PE .. +PE-1 of input pixel (oi0+r-PADH,
+        // oj0+cc-PADW); zero outside the image and past CIN.
+        for (int e = tid; e < NPL * TR * TC; e += NTHREADS) {
+            const int p = e % NPL;
+            const int rc = e / NPL;
+            const int cc = rc % TC, r = rc / TC;
+            const int ii = oi0 + r - PADH, jj = oj0 + cc - PADW;
+            const int ch = kci * KC + p * PE;
+            float v[PE];
+            const bool in = ii >= 0 && ii < HI && jj >= 0 && jj < WI;
+            const float* src = Ib + ((long)ii * WI + jj) * CIN + ch;
+#if CIN % PE == 0
+            if (in && ch < CIN) {
+#pragma unroll
+                for (int q = 0; q < PE; q += 4) {
+                    const rg_f32x4 x4 = *(const rg_f32x4*)(src + q);
+                    v[q] = x4[0]; v[q + 1] = x4[1]; v[q + 2] = x4[2]; v[q + 3] = x4[3];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < PE; ++q) v[q] = 0.f;
+            }
+#else
+#pragma unroll
+            for (int q = 0; q < PE; ++q) v[q] = (in && ch + q < CIN) ? src[q] : 0.f;
+#endif
+            tile[(p * TR + r) * TCP + cc] = rg_cell(v);
+        }
+        __syncthreads();
+
+        // cell offset of step s relative to the lane's first cell
+        auto step_off = [](int s) -> int {
+            const int u = s / NSTEP, t = s % NSTEP;
+            return RUN_PLANE(E * t) * PLANE + RUN_TAP(E * t) + u * TCP;
+        };
+        // A fragments one step ahead of the products that use them
+        rg_u32x4 a[2][MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[0][mt] = tile[lb + mt * MR * TCP];
+
+        // One step: read the next step's A fragments, the products of this
+        // one, then refill this ring slot with the fragments PF steps ahead
+        // (the packed bank has PF zero steps after each chunk, so the refill
+        // needs no bounds test; nor does the A read, whose step is clamped).
+        auto step = [&](const int s, const int r, const int ab) {
+            const int sn = s + 1 < KSTEPS ? s + 1 : KSTEPS - 1;
+            const int so = step_off(sn);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) a[ab ^ 1][mt] = tile[lb + so + mt * MR * TCP];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) rg_mma(acc[mt][nt], a[ab][mt], bq[r][nt]);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) bq[r][nt] = bc[((long)nt * NCHUNK * KSTEPS2 + s + PF) * 64];
+            // Keep this order (LDS reads, products, refill loads) and keep
+            // each step's instructions within the step: left free, the
+            // scheduler sinks the refills next to their use, which leaves
+            // the ring one step deep.
+            __builtin_amdgcn_sched_group_barrier(0x100, MT, 0);        // LDS reads
+            __builtin_amdgcn_sched_group_barrier(0x008, MT * NT * (DT == 0 ? 4 : 1), 0);   // products
+            __builtin_amdgcn_sched_group_barrier(0x020, NT, 0);        // global loads
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        // whole groups of 2*PF steps (ring slot and A buffer repeat with
+        // that period), then the remainder, unrolled
+        constexpr int G = 2 * PF;
+#if defined(FB_UNR) && FB_UNR
+#pragma unroll
+#else
+#pragma unroll 1
+#endif
+        for (int base = 0; base < KSTEPS / G * G; base += G) {
+#pragma unroll
+            for (int r2 = 0; r2 < G; ++r2) step(base + r2, r2 % PF, r2 & 1);
+        }
+#pragma unroll
+        for (int r2 = 0; r2 < KSTEPS % G; ++r2) step(KSTEPS / G * G + r2, r2 % PF, r2 & 1);
+    }
+
+    // Epilogue.  Accumulator layouts: 32x32 -- lane l, register r holds tile
+    // row 8*(r/4) + 4*(l/32) + r%4 and column l%32; 16x16 -- row 4*(l/16) + r
+    // and column l%16.
+    float* const Ob = O + (long)b * HO * WO * COUT;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int cc = c0 + (wn * NT + nt) * MF + lr;
+#if DT != 0
+        const float us = (cc < COUT) ? UNSCALE[cc] : 0.f;
+#endif
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int r = 0; r < NREG; ++r) {
+#if MF == 32
+                const int m = 8 * (r >> 2) + 4 * g + (r & 3);
+#else
+                const int m = 4 * g + r;
+#endif
+                const int oi = oi0 + (wm * MT + mt) * MR + m / MC;
+                const int oj = oj0 + m % MC;
+                if (oi < HO && oj < WO && cc < COUT) {
+#if DT == 0
+                    float val = acc[mt][nt][r];
+#else
+                    float val = acc[mt][nt][r] * us;
+#endif
+#ifdef FB_EPILOGUE
+                    val = FB_EPILOGUE(val, cc);
+#endif
+                    Ob[(oi * WO + oj) * COUT + cc] = val;
+                }
+            }
+        }
+    }
+}
+#endif  // !FB_PACK_FRAG

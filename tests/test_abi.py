@@ -136,6 +136,29 @@ def test_kernel_knobs_accepted_and_checked():
         codegen(lp, "forward", "algo=igemm kc=8 swz=1")                # 8-channel chunks
 
 
+def test_rgemm_knobs_accepted_and_checked():
+    """The register-streamed kernel's knobs reach the generated options of
+    the main kernel and of its filter pack (the pack flips the bank for the
+    input gradient); impossible values are refused before compiling."""
+    from paper_0911_3456_amd import FbcorrError, codegen, make_desc
+    lp = make_desc(1, 512, 512, 16, 128, 13, 13, precision="bf16")
+    _, o = codegen(lp, "forward", "algo=rgemm mf=32 kc=16 mr=2 mt=4 nt=2 wm=2 wn=2 pf=3 wpe=2")
+    for k in ("-DFB_KNAME=fbcorr_fwd_rgemm", "-DFB_DT=1", "-DFB_MF=32", "-DFB_KC=16", "-DFB_PF=3", "-DFB_WPE=2"):
+        assert k in o, k
+    d = make_desc(2, 45, 77, 16, 64, 7, 7)
+    _, o = codegen(d, "backward_x", "algo=rgemm mf=16 kc=16 mr=1 mt=8 nt=1 wm=4 wn=1")
+    assert "-DFB_KNAME=fbcorr_dx_rgemm" in o and "-DFB_PADH=6" in o and "-DFB_CIN=64" in o and "-DFB_COUT=16" in o
+    for role, cfg in [("forward", "algo=rgemm kc=12"),            # not the cell width times a power of two
+                      ("forward", "algo=rgemm mf=8"),
+                      ("forward", "algo=rgemm mr=3"),
+                      ("forward", "algo=rgemm pf=9"),
+                      ("forward", "algo=rgemm mt=8 nt=4 wpe=2"),  # accumulators over the register budget
+                      ("forward", "algo=rgemm flip=1"),           # flip is the input gradient's
+                      ("backward_w", "algo=rgemm")]:
+        with pytest.raises(FbcorrError):
+            codegen(lp if role == "forward" else d, role, cfg)
+
+
 def test_compile_error_is_reported():
     """An injected code-generation failure comes back as FBCORR_ERR_COMPILE
     with the compiler log, and the library stays usable."""
@@ -196,6 +219,22 @@ def test_gpu_test_configurations_are_valid():
     for c in tp.LOWP_CFGS:
         if c:
             fb.codegen(d, "forward", c)
+    import test_gpu_rgemm as tr
+    d = fb.make_desc(2, 45, 77, 8, 64, 9, 9)
+    for c in tr.RGEMM_CFGS:
+        fb.codegen(d, "forward", "algo=rgemm " + c)
+    for prec in ("bf16", "fp16"):
+        d = fb.make_desc(1, 50, 61, 32, 128, 7, 7, precision=prec)
+        for c in tr.LOWP_CFGS:
+            fb.codegen(d, "forward", "algo=rgemm " + c)
+    for sh in tr.SHAPES:
+        for prec in ("fp32", "bf16", "fp16"):
+            fb.codegen(fb.make_desc(*sh, precision=prec), "forward", "algo=rgemm")
+    d = fb.make_desc(2, 41, 67, 16, 64, 7, 7)
+    for c in tr.DX_CFGS:
+        fb.codegen(d, "backward_x", ("algo=rgemm " + c).strip())
+    for sh in tr.DX_SHAPES:
+        fb.codegen(fb.make_desc(*sh), "backward_x", "algo=rgemm")
 
 
 def test_disk_cache_reuse_and_corruption(tmp_path, monkeypatch):
