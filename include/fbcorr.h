@@ -161,6 +161,25 @@ FBCORR_API fbcorr_status fbcorr_workspace_size(fbcorr_plan_t plan, int pass, siz
 FBCORR_API fbcorr_status fbcorr_forward(fbcorr_plan_t plan, const float* x, const float* w, float* y,
                              void* workspace, size_t workspace_bytes, void* stream);
 
+/* fbcorr_forward_noalloc: fbcorr_forward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Runs the same kernels with the
+ * forward role's scratch -- the packed filter bank of the 16-bit and
+ * register-streamed matrix-core kernels, or the tap-major filter copy of the
+ * direct kernel's scalar-weight variant -- taken from a static device array
+ * of 16 MiB instead of a caller workspace; it calls no allocator.  Each GPU
+ * the library runs on holds its own array until the process ends (its
+ * address is looked up once per device, on the first call there).  Every
+ * call on one GPU shares that GPU's array: calls whose work overlaps on one
+ * GPU (other streams, other threads, other plans) race and must be
+ * serialised by the caller.  The kernels write every scratch byte they
+ * read, so nothing needs clearing between calls.  A plan whose forward role
+ * needs more than 16 MiB of scratch (fbcorr_workspace_size pass 0) gets
+ * FBCORR_ERR_WORKSPACE and nothing is launched.  x, w, y as for
+ * fbcorr_forward. */
+FBCORR_API fbcorr_status fbcorr_forward_noalloc(fbcorr_plan_t plan, const float* x, const float* w, float* y,
+                                                void* stream);
+
 /* fbcorr_backward: gradients of L = sum(dy * y) (the adjoint of the forward
  * map; the paper has no backward pass):
  *   dx[b,p,q,d] = sum_n sum_{u,v: 0<=p-u<Ho, 0<=q-v<Wo} dy[b,p-u,q-v,n] * w[n,u,v,d]

@@ -28,7 +28,7 @@ ROLES = {"forward": 0, "backward_x": 1, "backward_w": 2}
 
 # Every entry point declared in include/fbcorr.h.
 EXPORTS = (
-    "fbcorr_plan", "fbcorr_plan_destroy", "fbcorr_workspace_size", "fbcorr_forward",
+    "fbcorr_plan", "fbcorr_plan_destroy", "fbcorr_workspace_size", "fbcorr_forward", "fbcorr_forward_noalloc",
     "fbcorr_backward", "fbcorr_tune", "fbcorr_plan_batched", "fbcorr_forward_batched",
     "fbcorr_plan_get_config", "fbcorr_plan_set_config", "fbcorr_plan_set_epilogue", "fbcorr_plan_enable_timing",
     "fbcorr_plan_read_timing", "fbcorr_codegen", "fbcorr_compile_check", "fbcorr_compile_check_batched",

@@ -99,6 +99,17 @@ class Plan:
                                           ctypes.c_void_p(_stream_handle(self.device))))
         return y
 
+    def forward_noalloc(self, x: torch.Tensor, w: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        """fbcorr_forward_noalloc: the forward pass with the library's static
+        device scratch instead of a workspace (y must be given: nothing is
+        allocated)."""
+        _check_tensor(x, self.x_shape, "x")
+        _check_tensor(w, self.w_shape, "w")
+        _check_tensor(y, self.y_shape, "y")
+        nat.check(self.lib.fbcorr_forward_noalloc(self.handle, _ptr(x), _ptr(w), _ptr(y),
+                                                  ctypes.c_void_p(_stream_handle(self.device))))
+        return y
+
     def backward(self, x, w, dy, need_dx=True, need_dw=True, dx=None, dw=None):
         _check_tensor(dy, self.y_shape, "dy")
         if need_dx:
