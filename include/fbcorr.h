@@ -73,7 +73,13 @@ typedef enum fbcorr_status {
 /* Operand precision.  Accumulation and outputs are float32 in every mode.
  * BF16 and FP16 round x and w to nearest-even after scaling each filter by a
  * power of two, s_n = 2^-floor(log2 max|w[n]|), and divide the accumulated
- * result by s_n again (exact). */
+ * result by s_n again (exact).  FP16 inputs keep their full float32 range:
+ * every FP16 forward first takes max|x| over the whole input (an extra read
+ * of x), and when it reaches 2^15 the input is scaled by 2^-k while staged
+ * (max|x| * 2^-k < 2^15) and the outputs by 2^k, both exact; below 2^15
+ * (k = 0) nothing changes.  Values that the scale pushes below fp16's
+ * subnormal range round to zero, as any fp16 rounding would at that
+ * magnitude relative to the tensor's maximum.  Inputs must be finite. */
 typedef enum fbcorr_precision {
     FBCORR_FP32 = 0,
     FBCORR_BF16 = 1,
@@ -84,7 +90,10 @@ typedef enum fbcorr_precision {
  * block of outputs from LDS-staged input tiles and filter slices.  IGEMM:
  * implicit GEMM on the matrix cores, C[pixel, filter] = A[pixel, (u,v,d)] *
  * B[(u,v,d), filter], with A gathered from LDS-staged input tiles and never
- * materialised.  AUTO: the tuned choice, else IGEMM. */
+ * materialised; two kernels implement it (configuration algo=igemm: filter
+ * slices staged through LDS; algo=rgemm: filters repacked in matrix-core
+ * fragment order and streamed from L2 into registers), the tuning database
+ * or fbcorr_plan_set_config picks one.  AUTO: the tuned choice, else IGEMM. */
 typedef enum fbcorr_algo {
     FBCORR_ALGO_AUTO = 0,
     FBCORR_ALGO_DIRECT = 1,

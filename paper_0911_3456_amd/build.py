@@ -29,9 +29,12 @@ NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 # Representative specialisations used only for the offline compile check.
 CHECK_DEFINES = {
-    "igemm.hip": "-DFB_BATCH=1 -DFB_FH=9 -DFB_FW=9 -DFB_CIN=8 -DFB_COUT=64 -DFB_HI=256 -DFB_WI=256 -DFB_HO=248 -DFB_WO=248 "
-                 "-DFB_PADH=0 -DFB_PADW=0 -DFB_MF=32 -DFB_KC=8 -DFB_S=1 -DFB_MR=1 -DFB_KS=1 -DFB_MT=1 -DFB_NT=2 -DFB_WM=4 -DFB_WN=1 -DFB_DT=0 -DFB_XPAD=4 "
-                 "-DFB_WPAD=4 -DFB_USTAGE=1 -DFB_XCDMAP=1 -DFB_EPILOGUE(v,c)=fmaxf(v,0.f)",
+    "igemm.hip": ["-DFB_BATCH=1 -DFB_FH=9 -DFB_FW=9 -DFB_CIN=8 -DFB_COUT=64 -DFB_HI=256 -DFB_WI=256 -DFB_HO=248 -DFB_WO=248 "
+                  "-DFB_PADH=0 -DFB_PADW=0 -DFB_MF=32 -DFB_KC=8 -DFB_S=1 -DFB_MR=1 -DFB_KS=1 -DFB_MT=1 -DFB_NT=2 -DFB_WM=4 -DFB_WN=1 -DFB_DT=0 -DFB_XPAD=4 "
+                  "-DFB_WPAD=4 -DFB_USTAGE=1 -DFB_XCDMAP=1 -DFB_EPILOGUE(v,c)=fmaxf(v,0.f)",
+                  "-DFB_BATCH=1 -DFB_FH=13 -DFB_FW=13 -DFB_CIN=16 -DFB_COUT=128 -DFB_HI=512 -DFB_WI=512 -DFB_HO=500 -DFB_WO=500 "
+                  "-DFB_PADH=0 -DFB_PADW=0 -DFB_MF=32 -DFB_KC=16 -DFB_S=1 -DFB_MR=2 -DFB_KS=1 -DFB_MT=2 -DFB_NT=1 -DFB_WM=8 -DFB_WN=1 -DFB_DT=2 -DFB_XPAD=24 "
+                  "-DFB_WPAD=8 -DFB_USTAGE=1 -DFB_XCDMAP=1 -DFB_XMOFF=128"],
     "direct.hip": ["-DFB_BATCH=1 -DFB_FH=9 -DFB_FW=9 -DFB_D=8 -DFB_N=64 -DFB_H=256 -DFB_W=256 -DFB_HO=248 -DFB_WO=248 "
                    "-DFB_TH=8 -DFB_TW=32 -DFB_P=4 -DFB_Q=16 -DFB_NB=64 -DFB_DS=1 -DFB_LAYOUT=1 -DFB_XPAD=1 -DFB_WPAD=4 "
                    "-DFB_UD=1 -DFB_XCDMAP=1 -DFB_EPILOGUE(v,c)=fmaxf(v,0.f)",
@@ -60,10 +63,13 @@ CHECK_DEFINES = {
                   "-DFB_BATCH=1 -DFB_FH=5 -DFB_FW=5 -DFB_CIN=3 -DFB_COUT=7 -DFB_HI=20 -DFB_WI=19 -DFB_HO=16 "
                   "-DFB_WO=15 -DFB_PADH=0 -DFB_PADW=0 -DFB_DT=2 -DFB_KC=8 -DFB_MR=1 -DFB_MT=1 -DFB_NT=1 -DFB_WM=1 "
                   "-DFB_WN=1 -DFB_PF=2 -DFB_XPADC=1 -DFB_WPE=1 -DFB_XCDMAP=0 -DFB_KNAME=fbcorr_fwd_rgemm",
+                  "-DFB_BATCH=1 -DFB_FH=13 -DFB_FW=13 -DFB_CIN=16 -DFB_COUT=128 -DFB_HI=512 -DFB_WI=512 -DFB_HO=500 "
+                  "-DFB_WO=500 -DFB_PADH=0 -DFB_PADW=0 -DFB_DT=2 -DFB_KC=16 -DFB_MR=2 -DFB_MT=4 -DFB_NT=2 -DFB_WM=2 "
+                  "-DFB_WN=2 -DFB_PF=3 -DFB_XPADC=0 -DFB_WPE=2 -DFB_XCDMAP=1 -DFB_KNAME=fbcorr_fwd_rgemm -DFB_XMOFF=128",
                   "-DFB_PACK_FRAG -DFB_FH=13 -DFB_FW=13 -DFB_CIN=16 -DFB_COUT=128 -DFB_DT=1 -DFB_KC=16 -DFB_PF=3",
                   "-DFB_PACK_FRAG -DFB_FH=7 -DFB_FW=7 -DFB_CIN=64 -DFB_COUT=16 -DFB_DT=0 -DFB_KC=16 -DFB_PF=3 -DFB_FLIP"],
     "util.hip": "-DFB_SUM_PARTIALS -DFB_L=41472 -DFB_NP=256 -DFB_RS=16 -DFB_LANES=16 -DFB_FLIP_FILTERS -DFB_N=64 -DFB_FH=9 -DFB_FW=9 -DFB_D=8 "
-                "-DFB_PACK_LOWP -DFB_LOWP=1 -DFB_FILL_INT -DFB_TRANSPOSE_FILTERS -DFB_NPAD=64",
+                "-DFB_PACK_LOWP -DFB_LOWP=1 -DFB_FILL_INT -DFB_TRANSPOSE_FILTERS -DFB_NPAD=64 -DFB_ABSMAX",
 }
 
 

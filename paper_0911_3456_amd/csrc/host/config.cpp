@@ -472,6 +472,24 @@ static KernelSource util_source(const char* name, const char* define) {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// fp16 forward: the per-tensor input scale (reading c-10).  64 partial
+// maxima of |x| from fbcorr_absmax, written after `ucount` unscale floats,
+// are combined by the correlation kernel (option FB_XMOFF).  Returns the
+// bytes of the unscale + partials region.
+static const int kInputMaxParts = 64;
+static size_t add_input_scale(const fbcorr_desc& d, int dt, size_t ucount, RoleBuild& rb) {
+    if (dt != 2) return align256(ucount * 4);
+    const size_t xmoff = (ucount + 63) / 64 * 64;
+    rb.main.options.push_back("-DFB_XMOFF=" + std::to_string(xmoff));
+    KernelSource ks = util_source("fbcorr_absmax", "ABSMAX");
+    rb.aux.push_back(ks);
+    rb.aux_geom.push_back(LaunchGeom{kInputMaxParts, 1, 256, 0});
+    rb.ws_xmax = rb.ws_unscale + xmoff * 4;
+    rb.nxp = kInputMaxParts;
+    (void)d;
+    return align256((xmoff + kInputMaxParts) * 4);
+}
+
 static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, const DeviceInfo& di,
                             RoleBuild& rb, std::string& err);
 
@@ -545,7 +563,7 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
             rb.aux_geom.push_back(pg);
             rb.ws_lowp_w = 0;
             rb.ws_unscale = align256(bank);
-            rb.ws_bytes = rb.ws_unscale + align256((size_t)pg.grid_x * 4);
+            rb.ws_bytes = rb.ws_unscale + add_input_scale(d, dt, (size_t)pg.grid_x, rb);
             return true;
         } else {
             err = "forward role needs algo=igemm, algo=rgemm or algo=direct";
@@ -559,7 +577,7 @@ static bool build_role_impl(const fbcorr_desc& d, int role, const Config& c, con
             rb.aux_geom.push_back(LaunchGeom{d.N, 1, 256, 0});
             rb.ws_lowp_w = 0;
             rb.ws_unscale = align256((size_t)d.N * K * 2);
-            rb.ws_bytes = rb.ws_unscale + align256((size_t)d.N * 4);
+            rb.ws_bytes = rb.ws_unscale + add_input_scale(d, dt, (size_t)d.N, rb);
         }
         return true;
     }

@@ -22,6 +22,8 @@ struct RoleBuild {
     std::vector<LaunchGeom> aux_geom;
     size_t ws_bytes = 0;
     size_t ws_lowp_w = 0, ws_unscale = 0;   // forward low-precision layout
+    size_t ws_xmax = 0;                     // fp16: partial maxima of |x| (aux[1])
+    int nxp = 0;                            //   their count (0: no input scale)
     int np = 0;                             // filter-gradient partial count
 };
 

@@ -141,6 +141,15 @@ fbcorr_status run_forward(Plan* p, const RoleExec& ex, const float* x, const flo
         if (st != FBCORR_OK) { timing_end(p, FBCORR_ROLE_FORWARD, s, ev); return st; }
         wt = wq;
         unscale = us;
+        if (rb.nxp > 0) {
+            // fp16: partial maxima of |x| for the per-tensor input scale
+            const fbcorr_desc& d = p->desc;
+            long n = (long)d.batch * d.H * d.W * d.D;
+            float* part = (float*)(base + rb.ws_xmax);
+            void* a1[] = {(void*)&x, &n, &part};
+            st = launch(ex.aux[1], rb.aux_geom[1], s, a1);
+            if (st != FBCORR_OK) { timing_end(p, FBCORR_ROLE_FORWARD, s, ev); return st; }
+        }
     }
     if (rb.cfg.algo == "direct") {
         void* args[] = {(void*)&x, (void*)&w, (void*)&y};

@@ -37,6 +37,10 @@
 //   problem  BATCH FH FW CIN COUT HI WI HO WO PADH PADW
 //   DT       0 fp32 operands, 1 bf16, 2 fp16 (B pre-scaled and rounded by
 //            the pack; UNSCALE[c] multiplies each output)
+//   XMOFF    fp16 only: UNSCALE[XMOFF .. XMOFF+63] hold partial maxima of |x|
+//            (fbcorr_absmax); when the input reaches 2^15 it is scaled by
+//            2^-k while staged (max |x| * 2^-k < 2^15, inside the fp16
+//            range) and the outputs by 2^k -- both exact powers of two
 //   tiling   MF (32 or 16: MFMA tile), KC (channels per chunk: PE times a
 //            power of two), MR (rows of an MF-pixel tile), MT NT (tiles per
 //            wave), WM WN (waves), PF (filter-fragment ring depth in steps),
@@ -107,26 +111,101 @@ static_assert(KC % PE == 0 && ((KC / PE) & (KC / PE - 1)) == 0, "KC must be PE t
 extern "C" __global__ void __launch_bounds__(256)
 fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* __restrict__ unscale)
 {
-    constexpr int K = FH * FW * CIN;
+    // items: (chunk, filter row, tap slot, plane), plane fastest; a thread
+    // takes items tid, tid + 256, ...  When they fit (HELD), every item's
+    // values are loaded once, all loads in flight together, and kept for
+    // both the maximum and the packing; otherwise they are read twice.
+    constexpr int ITEMS = NCHUNK * FH * NTAPS * NPL;
+    constexpr int PER = (ITEMS + 255) / 256;
+    constexpr bool HELD = PER * PE <= 64;
     const int c = blockIdx.x;
     const int j = c / MF, col = c % MF;
     const bool real = c < COUT;
-    auto src = [&](int u, int v, int ch) -> float {
-#ifdef FB_FLIP
-        return w[(((long)ch * FH + (FH - 1 - u)) * FW + (FW - 1 - v)) * COUT + c];
+    auto load_item = [&](int e, float* vals) {
+        const int p = e % NPL;
+        int r = e / NPL;
+        const int vv = r % NTAPS;
+        r /= NTAPS;
+        const int u = r % FH, kci = r / FH;
+        const int ch0 = kci * KC + p * PE;
+        const bool ok = e < ITEMS && real && vv < FW;
+#if !defined(FB_FLIP) && CIN % PE == 0
+        // PE consecutive channels of one tap: contiguous in w[c][u][v][:]
+        if (ok && ch0 < CIN) {
+            const float* src = w + (((long)c * FH + u) * FW + vv) * CIN + ch0;
+#pragma unroll
+            for (int q = 0; q < PE; q += 4) {
+                const rg_f32x4 x4 = *(const rg_f32x4*)(src + q);
+                vals[q] = x4[0]; vals[q + 1] = x4[1]; vals[q + 2] = x4[2]; vals[q + 3] = x4[3];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PE; ++i) vals[i] = 0.f;
+        }
 #else
-        return w[(((long)c * FH + u) * FW + v) * CIN + ch];
+#pragma unroll
+        for (int i = 0; i < PE; ++i) {
+            const int ch = ch0 + i;
+#ifdef FB_FLIP
+            vals[i] = (ok && ch < CIN) ? w[(((long)ch * FH + (FH - 1 - u)) * FW + (FW - 1 - vv)) * COUT + c] : 0.f;
+#else
+            vals[i] = (ok && ch < CIN) ? w[(((long)c * FH + u) * FW + vv) * CIN + ch] : 0.f;
+#endif
+        }
 #endif
     };
+    auto store_item = [&](int e, const float* vals, float sc) {
+        if (e >= ITEMS) return;
+        const int p = e % NPL;
+        int r = e / NPL;
+        const int vv = r % NTAPS;
+        r /= NTAPS;
+        const int u = r % FH, kci = r / FH;
+        const int el = vv * KC + p * PE;          // position in the row's run
+        const int t = el / E, g = (el % E) / PE;
+        rg_u32x4 cell;
+#if DT == 0
+        (void)sc;
+        cell = __builtin_bit_cast(rg_u32x4, (rg_f32x4){vals[0], vals[1], vals[2], vals[3]});
+#else
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float lo_v = vals[2 * i] * sc, hi_v = vals[2 * i + 1] * sc;   // exact: power of two
+#if DT == 1
+            const unsigned lo = __builtin_bit_cast(unsigned short, (__bf16)lo_v);
+            const unsigned hi = __builtin_bit_cast(unsigned short, (__bf16)hi_v);
+#else
+            const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)lo_v);
+            const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)hi_v);
+#endif
+            cell[i] = lo | (hi << 16);
+        }
+#endif
+        bp[(((long)j * NCHUNK + kci) * KSTEPS2 + u * NSTEP + t) * 64 + g * MF + col] = cell;
+    };
+
+    float held[HELD ? PER : 1][PE];
+    float m = 0.f;
+    if (HELD) {
+#pragma unroll
+        for (int i = 0; i < (HELD ? PER : 1); ++i) load_item(threadIdx.x + i * 256, held[i]);
+#pragma unroll
+        for (int i = 0; i < (HELD ? PER : 1); ++i)
+#pragma unroll
+            for (int q = 0; q < PE; ++q) m = fmaxf(m, fabsf(held[i][q]));
+    } else {
+        for (int e = threadIdx.x; e < ITEMS; e += 256) {
+            float vals[PE];
+            load_item(e, vals);
+#pragma unroll
+            for (int q = 0; q < PE; ++q) m = fmaxf(m, fabsf(vals[q]));
+        }
+    }
     float sc = 1.0f;
 #if DT != 0
+    // e_c = floor(log2 max|w[c]|) over the filter's values (the padding
+    // zeros change nothing)
     __shared__ float red[4];
-    float m = 0.f;
-    if (real)
-        for (int k = threadIdx.x; k < K; k += 256) {
-            const int ch = k % CIN, v = (k / CIN) % FW, u = k / (CIN * FW);
-            m = fmaxf(m, fabsf(src(u, v, ch)));
-        }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -141,40 +220,17 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
     if (threadIdx.x == 0) unscale[c] = real ? ldexpf(1.0f, ex) : 0.f;
 #else
     (void)unscale;
+    (void)m;
 #endif
-    // items: (chunk, filter row, tap slot, plane), plane fastest
-    constexpr int ITEMS = NCHUNK * FH * NTAPS * NPL;
-    for (int e = threadIdx.x; e < ITEMS; e += 256) {
-        const int p = e % NPL;
-        int r = e / NPL;
-        const int vv = r % NTAPS;
-        r /= NTAPS;
-        const int u = r % FH, kci = r / FH;
-        const int el = vv * KC + p * PE;          // position in the row's run
-        const int t = el / E, g = (el % E) / PE;
-        float vals[PE];
+    if (HELD) {
 #pragma unroll
-        for (int i = 0; i < PE; ++i) {
-            const int ch = kci * KC + p * PE + i;
-            vals[i] = (real && vv < FW && ch < CIN) ? src(u, vv, ch) * sc : 0.f;
+        for (int i = 0; i < (HELD ? PER : 1); ++i) store_item(threadIdx.x + i * 256, held[i], sc);
+    } else {
+        for (int e = threadIdx.x; e < ITEMS; e += 256) {
+            float vals[PE];
+            load_item(e, vals);
+            store_item(e, vals, sc);
         }
-        rg_u32x4 cell;
-#if DT == 0
-        cell = __builtin_bit_cast(rg_u32x4, (rg_f32x4){vals[0], vals[1], vals[2], vals[3]});
-#else
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#if DT == 1
-            const unsigned lo = __builtin_bit_cast(unsigned short, (__bf16)vals[2 * i]);
-            const unsigned hi = __builtin_bit_cast(unsigned short, (__bf16)vals[2 * i + 1]);
-#else
-            const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)vals[2 * i]);
-            const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)vals[2 * i + 1]);
-#endif
-            cell[i] = lo | (hi << 16);
-        }
-#endif
-        bp[(((long)j * NCHUNK + kci) * KSTEPS2 + u * NSTEP + t) * 64 + g * MF + col] = cell;
     }
     // the zero steps after each chunk (read by the ring's last refills)
     for (int e = threadIdx.x; e < NCHUNK * (KSTEPS2 - KSTEPS) * NKG; e += 256) {
@@ -218,10 +274,15 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
 #define PLANE (TR * TCP)              // cells per plane
 #define TILE_CELLS (NPL * PLANE)
 #define NTHREADS (WM * WN * 64)
+// tile cells staged per thread and batch (all of them when they are few)
+#define SCELLS ((NPL * TR * TC + NTHREADS - 1) / NTHREADS)
+#define SB (SCELLS < (DT == 0 ? 16 : 8) ? SCELLS : (DT == 0 ? 16 : 8))
 
 static_assert(MF % MR == 0, "MR must divide MF");
 static_assert(PF >= 1, "ring depth");
 static_assert(CIN % PE == 0 || KC == PE, "partial cells need KC == PE");
+
+template <bool V> struct RgBool { static constexpr bool value = V; };
 
 #if MF == 32
 typedef rg_f32x16 rg_acc;
@@ -229,19 +290,38 @@ typedef rg_f32x16 rg_acc;
 typedef rg_f32x4 rg_acc;
 #endif
 
-__device__ __forceinline__ rg_u32x4 rg_cell(const float* v) {
+// fp16 input scale exponent k >= 0 from the 64 partial maxima of |x| (one
+// per lane of the wave, combined by shuffles; the same in every lane).
+__device__ __forceinline__ int rg_input_scale_exp(const float* __restrict__ UNSCALE) {
+#if DT == 2 && defined(FB_XMOFF)
+    float m = UNSCALE[FB_XMOFF + (threadIdx.x & 63)];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    int e = 0;
+    if (m >= 32768.f) (void)frexpf(m, &e);    // m < 2^e
+    return e > 15 ? e - 15 : 0;
+#else
+    (void)UNSCALE;
+    return 0;
+#endif
+}
+
+// One 16-byte cell of PE values (scaled by xs, exact) in the operand type.
+__device__ __forceinline__ rg_u32x4 rg_cell(const float* v, const float xs) {
     rg_u32x4 c;
 #if DT == 0
+    (void)xs;
     c = __builtin_bit_cast(rg_u32x4, (rg_f32x4){v[0], v[1], v[2], v[3]});
 #else
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #if DT == 1
+        (void)xs;
         const unsigned lo = __builtin_bit_cast(unsigned short, (__bf16)v[2 * i]);      // nearest even
         const unsigned hi = __builtin_bit_cast(unsigned short, (__bf16)v[2 * i + 1]);
 #else
-        const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)v[2 * i]);
-        const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)v[2 * i + 1]);
+        const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)(v[2 * i] * xs));
+        const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)(v[2 * i + 1] * xs));
 #endif
         c[i] = lo | (hi << 16);
     }
@@ -324,6 +404,15 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
 #pragma unroll
             for (int r = 0; r < NREG; ++r) acc[mt][nt][r] = 0.f;
 
+    // fp16: per-tensor input scale 2^-kx (1 unless the input reaches 2^15)
+#if DT == 2
+    const int kx = rg_input_scale_exp(UNSCALE);
+    const float xs = ldexpf(1.f, -kx), ys = ldexpf(1.f, kx);
+#else
+    const float xs = 1.f, ys = 1.f;
+#endif
+    (void)ys;
+
 #pragma unroll 1
     for (int kci = 0; kci < NCHUNK; ++kci) {
         const rg_u32x4* bc = bw + (long)kci * KSTEPS2 * 64;
@@ -337,32 +426,46 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
         if (kci > 0) __syncthreads();        // every wave is done with the previous chunk
         // Stage the chunk's input tile: cell (plane p, row r, column cc) =
         // channels kci*KC + p*PE .. +PE-1 of input pixel (oi0+r-PADH,
-        // oj0+cc-PADW); zero outside the image and past CIN.
-        for (int e = tid; e < NPL * TR * TC; e += NTHREADS) {
-            const int p = e % NPL;
-            const int rc = e / NPL;
-            const int cc = rc % TC, r = rc / TC;
-            const int ii = oi0 + r - PADH, jj = oj0 + cc - PADW;
-            const int ch = kci * KC + p * PE;
-            float v[PE];
-            const bool in = ii >= 0 && ii < HI && jj >= 0 && jj < WI;
-            const float* src = Ib + ((long)ii * WI + jj) * CIN + ch;
+        // oj0+cc-PADW); zero outside the image and past CIN.  In batches of
+        // SB cells per thread, every load of a batch issued before the
+        // first conversion (one memory latency per batch, not per cell).
+#pragma unroll 1
+        for (int e0 = 0; e0 < NPL * TR * TC; e0 += SB * NTHREADS) {
+            float v[SB][PE];
+#pragma unroll
+            for (int i = 0; i < SB; ++i) {
+                const int e = e0 + i * NTHREADS + tid;
+                const int p = e % NPL;
+                const int rc = e / NPL;
+                const int cc = rc % TC, r = rc / TC;
+                const int ii = oi0 + r - PADH, jj = oj0 + cc - PADW;
+                const int ch = kci * KC + p * PE;
+                const bool in = e < NPL * TR * TC && ii >= 0 && ii < HI && jj >= 0 && jj < WI;
+                const float* src = Ib + ((long)ii * WI + jj) * CIN + ch;
 #if CIN % PE == 0
-            if (in && ch < CIN) {
+                if (in && ch < CIN) {
 #pragma unroll
-                for (int q = 0; q < PE; q += 4) {
-                    const rg_f32x4 x4 = *(const rg_f32x4*)(src + q);
-                    v[q] = x4[0]; v[q + 1] = x4[1]; v[q + 2] = x4[2]; v[q + 3] = x4[3];
+                    for (int q = 0; q < PE; q += 4) {
+                        const rg_f32x4 x4 = *(const rg_f32x4*)(src + q);
+                        v[i][q] = x4[0]; v[i][q + 1] = x4[1]; v[i][q + 2] = x4[2]; v[i][q + 3] = x4[3];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < PE; ++q) v[i][q] = 0.f;
                 }
-            } else {
-#pragma unroll
-                for (int q = 0; q < PE; ++q) v[q] = 0.f;
-            }
 #else
 #pragma unroll
-            for (int q = 0; q < PE; ++q) v[q] = (in && ch + q < CIN) ? src[q] : 0.f;
+                for (int q = 0; q < PE; ++q) v[i][q] = (in && ch + q < CIN) ? src[q] : 0.f;
 #endif
-            tile[(p * TR + r) * TCP + cc] = rg_cell(v);
+            }
+#pragma unroll
+            for (int i = 0; i < SB; ++i) {
+                const int e = e0 + i * NTHREADS + tid;
+                const int p = e % NPL;
+                const int rc = e / NPL;
+                const int cc = rc % TC, r = rc / TC;
+                if (e < NPL * TR * TC) tile[(p * TR + r) * TCP + cc] = rg_cell(v[i], xs);
+            }
         }
         __syncthreads();
 
@@ -418,38 +521,44 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
 
     // Epilogue.  Accumulator layouts: 32x32 -- lane l, register r holds tile
     // row 8*(r/4) + 4*(l/32) + r%4 and column l%32; 16x16 -- row 4*(l/16) + r
-    // and column l%16.
+    // and column l%16.  Workgroups whose tile lies inside the output store
+    // without per-element bounds tests.
     float* const Ob = O + (long)b * HO * WO * COUT;
+    const bool interior = oi0 + TH <= HO && oj0 + TWO <= WO && c0 + CB <= COUT;
+    auto store_all = [&](auto checked) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int cc = c0 + (wn * NT + nt) * MF + lr;
+        for (int nt = 0; nt < NT; ++nt) {
+            const int cc = c0 + (wn * NT + nt) * MF + lr;
 #if DT != 0
-        const float us = (cc < COUT) ? UNSCALE[cc] : 0.f;
+            const float us = (!decltype(checked)::value || cc < COUT) ? UNSCALE[cc] * ys : 0.f;   // exact: powers of two
 #endif
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
+            for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-            for (int r = 0; r < NREG; ++r) {
+                for (int r = 0; r < NREG; ++r) {
 #if MF == 32
-                const int m = 8 * (r >> 2) + 4 * g + (r & 3);
+                    const int m = 8 * (r >> 2) + 4 * g + (r & 3);
 #else
-                const int m = 4 * g + r;
+                    const int m = 4 * g + r;
 #endif
-                const int oi = oi0 + (wm * MT + mt) * MR + m / MC;
-                const int oj = oj0 + m % MC;
-                if (oi < HO && oj < WO && cc < COUT) {
+                    const int oi = oi0 + (wm * MT + mt) * MR + m / MC;
+                    const int oj = oj0 + m % MC;
+                    if (!decltype(checked)::value || (oi < HO && oj < WO && cc < COUT)) {
 #if DT == 0
-                    float val = acc[mt][nt][r];
+                        float val = acc[mt][nt][r];
 #else
-                    float val = acc[mt][nt][r] * us;
+                        float val = acc[mt][nt][r] * us;
 #endif
 #ifdef FB_EPILOGUE
-                    val = FB_EPILOGUE(val, cc);
+                        val = FB_EPILOGUE(val, cc);
 #endif
-                    Ob[(oi * WO + oj) * COUT + cc] = val;
+                        Ob[(oi * WO + oj) * COUT + cc] = val;
+                    }
                 }
             }
         }
-    }
+    };
+    if (interior) store_all(RgBool<false>{});
+    else store_all(RgBool<true>{});
 }
 #endif  // !FB_PACK_FRAG

@@ -12,6 +12,9 @@
 //                        wq[n,k] = round_to_nearest_even(w[n,k] * 2^-e_n) as
 //                        bf16 (LOWP=1) or fp16 (LOWP=2), unscale[n] = 2^e_n
 //                        (an all-zero filter gets e_n = 0).
+//   fbcorr_absmax        part[g] = max |x[i]| over workgroup g's share of the
+//                        n input values (NXP workgroups): the fp16 forward's
+//                        per-tensor input scale is derived from these.
 //   fbcorr_fill_int      integer-valued pattern in [-R, R] (tuner gate data).
 //   fbcorr_transpose_filters  wt[((u*FW + v)*D + d)*NPAD + n] = w[n,u,v,d]
 //                        (zero for N <= n < NPAD): the filters of one tap
@@ -171,6 +174,29 @@ fbcorr_pack_lowp(const float* __restrict__ w, unsigned short* __restrict__ wq,
         for (int k = threadIdx.x; k < K; k += 256) put(k, wn[k]);
     }
     if (threadIdx.x == 0) unscale[n] = ldexpf(1.0f, ex);
+}
+#endif
+
+#ifdef FB_ABSMAX
+typedef float f32x4a __attribute__((ext_vector_type(4)));
+extern "C" __global__ void __launch_bounds__(256)
+fbcorr_absmax(const float* __restrict__ x, long n, float* __restrict__ part)
+{
+    // 16-byte loads where the data allows, then the scalar tail
+    __shared__ float red[4];
+    float m = 0.f;
+    const long n4 = (((unsigned long)x & 15) == 0) ? n / 4 : 0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long)gridDim.x * 256) {
+        const f32x4a v = ((const f32x4a*)x)[i];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+    }
+    for (long i = n4 * 4 + (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        m = fmaxf(m, fabsf(x[i]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 #endif
 

@@ -159,6 +159,19 @@ def test_rgemm_knobs_accepted_and_checked():
             codegen(lp if role == "forward" else d, role, cfg)
 
 
+def test_fp16_forward_has_input_scale():
+    """fp16 forward roles (both matrix-core algorithms) read the partial
+    maxima of |x| for the per-tensor input scale; bf16 and fp32 do not."""
+    from paper_0911_3456_amd import codegen, make_desc
+    for algo in ("igemm", "rgemm"):
+        _, o = codegen(make_desc(1, 40, 43, 16, 64, 7, 7, precision="fp16"), "forward", "algo=" + algo)
+        assert "-DFB_XMOFF=" in o
+        _, o = codegen(make_desc(1, 40, 43, 16, 64, 7, 7, precision="bf16"), "forward", "algo=" + algo)
+        assert "-DFB_XMOFF" not in o
+    _, o = codegen(make_desc(1, 40, 43, 16, 64, 7, 7), "forward", "algo=igemm")
+    assert "-DFB_XMOFF" not in o
+
+
 def test_compile_error_is_reported():
     """An injected code-generation failure comes back as FBCORR_ERR_COMPILE
     with the compiler log, and the library stays usable."""

@@ -112,3 +112,41 @@ def test_precision_workload_sampled():
         e, m, _ = sampled_forward_error(y, x, w, sites)
         print("precision workload", prec, algo, "max %.3e mean %.3e" % (e, m))
         assert e <= tol
+
+
+# fp16 inputs beyond its range: the per-tensor power-of-two input scale keeps
+# them finite (reading c-10); both matrix-core algorithms.
+FP16_RANGE_CFGS = ["algo=igemm", "algo=rgemm"]
+
+
+@pytest.mark.parametrize("cfg", FP16_RANGE_CFGS)
+def test_fp16_input_beyond_range_integer_exact(cfg):
+    """Integer inputs times 2^16 (up to 2^19, far past fp16's 65504): scaled
+    by 2^-5 while staged they stay integers below 2^15, so the result is
+    exact and equal to the oracle's."""
+    need_gpu()
+    s = wl.Shape(1, 37, 41, 16, 64, 5, 5)
+    x, w, _ = wl.draw_integer(s, seed=61)
+    x = (x * 65536.0).astype(np.float32)
+    plan = _plan(s, precision="fp16")
+    plan.set_config("forward", cfg)
+    y = host(plan.forward(*to_dev(x, w)))
+    assert np.isfinite(y).all()
+    np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
+
+
+@pytest.mark.parametrize("cfg", FP16_RANGE_CFGS)
+def test_fp16_input_beyond_range_error_bound(cfg):
+    """Random inputs scaled to +-3e5: finite, within the fp16 bound of the
+    oracle; unscaled inputs give the same result divided by the scale."""
+    need_gpu()
+    s = wl.Shape(1, 40, 43, 16, 64, 7, 7)
+    x, w, _ = wl.draw_single(s, seed=62)
+    big = (x * 3.0e5).astype(np.float32)
+    plan = _plan(s, precision="fp16")
+    plan.set_config("forward", cfg)
+    y = host(plan.forward(*to_dev(big, w)))
+    assert np.isfinite(y).all()
+    e, m, idx = forward_error(y, big, w)
+    print("fp16 %s, |x| up to 3e5: max %.3e mean %.3e at %s" % (cfg, e, m, idx))
+    assert e <= FP16_BOUND
