@@ -342,6 +342,7 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "PF", pf);
     opt(ks.options, "XPADC", xpadc); opt(ks.options, "WPE", wpe); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
     if (unr) opt(ks.options, "UNR", 1);
+    if (c.get("nts")) opt(ks.options, "NTS", 1);
     pack = KernelSource();
     pack.name = "fbcorr_pack_frag";
     pack.file = "rgemm";
@@ -507,7 +508,7 @@ static bool known_keys(const Config& c, std::string& err) {
                    "uunr", "swz"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
-        {"rgemm", {"mf", "kc", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip"}},
+        {"rgemm", {"mf", "kc", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip", "nts"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }

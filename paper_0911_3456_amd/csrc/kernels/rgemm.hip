@@ -46,7 +46,8 @@
 //            wave), WM WN (waves), PF (filter-fragment ring depth in steps),
 //            XPADC (LDS row padding in cells), WPE (waves per SIMD the
 //            register budget is sized for), UNR (1: unroll the step loop
-//            completely), XCDMAP (XCD-aware workgroup order)
+//            completely), XCDMAP (XCD-aware workgroup order), NTS (1:
+//            non-temporal output stores)
 //   naming   KNAME   EPILOGUE(v, c) as in the LDS-staged kernel
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
@@ -552,7 +553,17 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
 #ifdef FB_EPILOGUE
                         val = FB_EPILOGUE(val, cc);
 #endif
-                        Ob[(oi * WO + oj) * COUT + cc] = val;
+                        // unsigned 32-bit offset from the image's base: a
+                        // scalar base plus a vector offset per store
+                        float* const dst = Ob + (unsigned)((oi * WO + oj) * COUT + cc);
+#if defined(FB_NTS) && FB_NTS
+                        // streaming store: the output is not read again here,
+                        // and leaving L2 to the filter fragments and input
+                        // tiles that every workgroup re-reads
+                        __builtin_nontemporal_store(val, dst);
+#else
+                        *dst = val;
+#endif
                     }
                 }
             }
