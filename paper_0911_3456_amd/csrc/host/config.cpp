@@ -286,9 +286,12 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     const int wm = c.get("wm"), wn = c.get("wn"), pf = c.get("pf"), xpadc = c.get("xpadc");
     const int wpe = c.v.count("wpe") ? c.get("wpe") : 2, xcd = c.get("xcd"), unr = c.get("unr");
     const int mf = c.v.count("mf") ? c.get("mf") : 32;
+    const int sh = c.v.count("s") ? c.get("s") : 1;
     if (kc < 1 || mr < 1 || mt < 1 || nt < 1 || wm < 1 || wn < 1 || pf < 1 || xpadc < 0) {
         err = "rgemm: every knob must be positive"; return false;
     }
+    if (sh != 1 && sh != 2 && sh != 4 && sh != 8) { err = "rgemm: s must be 1, 2, 4 or 8"; return false; }
+    if ((wn * nt * mf) % sh) { err = "rgemm: the columns must split evenly into shifts"; return false; }
     if (mf != 32 && mf != 16) { err = "rgemm: mf must be 32 or 16"; return false; }
     if (pf > 8) { err = "rgemm: pf is at most 8"; return false; }
     if (wpe < 1 || wpe > 8) { err = "rgemm: wpe must be 1..8"; return false; }
@@ -308,21 +311,23 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     if (regs > 512 / wpe) {
         err = "rgemm: needs about " + std::to_string(regs) + " registers per lane, more than wpe allows"; return false;
     }
-    const int nstep = (fw * kc + e - 1) / e;
+    const int nstep = ((fw + sh - 1) * kc + e - 1) / e;
     const int ntaps = nstep * e / kc;
     const int nchunk = (cin + kc - 1) / kc;
     const int ksteps2 = fh * nstep + pf;
     const int mc = mf / mr;
-    const int th = wm * mt * mr, two = mc, cb = wn * nt * mf;
-    const int tr = th + fh - 1, tc = mc - 1 + ntaps, tcp = tc + xpadc;
+    const int ncolw = wn * nt * mf, cb = ncolw / sh;
+    const int th = wm * mt * mr, two = sh * mc;
+    const int tr = th + fh - 1, tc = sh * (mc - 1) + ntaps, tcp = tc + xpadc;
     const long lds = (long)npl * tr * tcp * 16;
     if (lds > di.lds_per_block) { err = "rgemm: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
     const int ho = hi + 2 * padh - fh + 1, wo = wi + 2 * padw - fw + 1;
     const long grid = (long)cdiv(wo, two) * cdiv(ho, th) * cdiv(cout, cb) * batch;
     if (grid <= 0 || grid > 0x7fffffffL) { err = "rgemm: grid out of range"; return false; }
-    // the packed bank covers whole column blocks of the correlation kernel:
-    // one kilobyte per column tile, chunk and step
-    const int ncols = cdiv(cout, cb) * cb;
+    // the packed bank covers whole column blocks of the correlation kernel
+    // (NCOLW columns of shifted filters each): one kilobyte per column tile,
+    // chunk and step
+    const int ncols = cdiv(cout, cb) * ncolw;
     bank_bytes = (size_t)(ncols / mf) * nchunk * ksteps2 * 1024;
     g.grid_x = (int)grid;
     g.grid_y = 1;
@@ -338,7 +343,7 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "HI", hi); opt(ks.options, "WI", wi); opt(ks.options, "HO", ho); opt(ks.options, "WO", wo);
     opt(ks.options, "PADH", padh); opt(ks.options, "PADW", padw); opt(ks.options, "DT", dt);
     opt(ks.options, "MF", mf); opt(ks.options, "KC", kc); opt(ks.options, "MR", mr);
-    opt(ks.options, "MT", mt); opt(ks.options, "NT", nt);
+    opt(ks.options, "MT", mt); opt(ks.options, "NT", nt); opt(ks.options, "S", sh);
     opt(ks.options, "WM", wm); opt(ks.options, "WN", wn); opt(ks.options, "PF", pf);
     opt(ks.options, "XPADC", xpadc); opt(ks.options, "WPE", wpe); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
     if (unr) opt(ks.options, "UNR", 1);
@@ -350,7 +355,8 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     pack.options.push_back("-DFB_PACK_FRAG");
     opt(pack.options, "FH", fh); opt(pack.options, "FW", fw); opt(pack.options, "CIN", cin);
     opt(pack.options, "COUT", cout); opt(pack.options, "DT", dt); opt(pack.options, "MF", mf);
-    opt(pack.options, "KC", kc); opt(pack.options, "PF", pf);
+    opt(pack.options, "KC", kc); opt(pack.options, "PF", pf); opt(pack.options, "S", sh);
+    opt(pack.options, "NCOLW", ncolw);
     pack_geom = LaunchGeom{ncols, 1, 256, 0};
     return true;
 }
@@ -508,7 +514,7 @@ static bool known_keys(const Config& c, std::string& err) {
                    "uunr", "swz"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
-        {"rgemm", {"mf", "kc", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip", "nts"}},
+        {"rgemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip", "nts"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }

@@ -153,8 +153,13 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
             const int rshapes[][4] = {{4, 2, 2, 2}, {4, 2, 1, 2}, {4, 2, 4, 1}, {2, 2, 2, 2}, {2, 2, 4, 2},
                                       {4, 1, 2, 4}, {4, 1, 4, 2}, {8, 1, 2, 2}, {2, 4, 2, 1}, {4, 2, 2, 1},
                                       {2, 2, 4, 1}, {4, 1, 4, 1}, {4, 4, 1, 2}, {2, 1, 4, 2}, {8, 1, 1, 4}};
+            // column shifts for banks narrower than a tile
+            std::vector<int> rss = {1};
+            for (int sv : {2, 4})
+                if (cout * sv <= 32) rss.push_back(sv);
             for (int kc : rkcs)
               for (int mf : {32, 16})
+               for (int sv : rss)
                 for (int mr : {1, 2, 4})
                     for (auto& sh : rshapes)
                         for (int pf : {2, 3, 4, 6})
@@ -163,9 +168,11 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                                   for (int nts : {0, 1}) {
                                     Config c = rb;
                                     c.v["nts"] = nts;
-                                    if (sh[1] * sh[3] * mf > std::max(mf, ((cout + mf - 1) / mf) * mf)) continue;
+                                    if (sh[1] * sh[3] * mf > std::max(mf, ((cout * sv + mf - 1) / mf) * mf)) continue;
                                     if (mf == 16 && cout > 64) continue;
+                                    if (sv > 1 && (sh[1] * sh[3] * mf) % sv) continue;
                                     c.v["mf"] = mf;
+                                    c.v["s"] = sv;
                                     c.v["kc"] = kc; c.v["mr"] = mr;
                                     c.v["mt"] = sh[0]; c.v["nt"] = sh[1]; c.v["wm"] = sh[2]; c.v["wn"] = sh[3];
                                     c.v["pf"] = pf; c.v["xpadc"] = xp; c.v["wpe"] = wpe;

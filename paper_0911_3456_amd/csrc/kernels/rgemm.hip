@@ -33,6 +33,13 @@
 // lane's cell in product q).  A and B use the same order, so every padding
 // value multiplies a zero weight.
 //
+// Column shift S (narrow outputs).  A workgroup's NCOLW = WN*NT*MF matrix
+// columns are S shifts x CB = NCOLW/S output channels: column (s, c)
+// computes output column S*j + s of base pixel column j, with filter
+// B[(u, v', k), (s, c)] = Wt[c, u, v'-s, k] (zero outside 0 <= v'-s < FW)
+// over NTAPF = FW+S-1 taps per filter row; the pack writes each shifted
+// copy, and a lane's A run starts at pixel column S*j.
+//
 // Compile-time constants (FB_<name>):
 //   problem  BATCH FH FW CIN COUT HI WI HO WO PADH PADW
 //   DT       0 fp32 operands, 1 bf16, 2 fp16 (B pre-scaled and rounded by
@@ -42,7 +49,8 @@
 //            2^-k while staged (max |x| * 2^-k < 2^15, inside the fp16
 //            range) and the outputs by 2^k -- both exact powers of two
 //   tiling   MF (32 or 16: MFMA tile), KC (channels per chunk: PE times a
-//            power of two), MR (rows of an MF-pixel tile), MT NT (tiles per
+//            power of two), S (column shift, below), MR (rows of an
+//            MF-pixel tile), MT NT (tiles per
 //            wave), WM WN (waves), PF (filter-fragment ring depth in steps),
 //            XPADC (LDS row padding in cells), WPE (waves per SIMD the
 //            register budget is sized for), UNR (1: unroll the step loop
@@ -80,10 +88,16 @@ typedef _Float16 rg_f16x8 __attribute__((ext_vector_type(8)));
 #else
 #define PE 8
 #endif
+#ifdef FB_S
+#define S FB_S
+#else
+#define S 1
+#endif
 #define NKG (64 / MF)             // lane groups of one instruction
 #define E (NKG * PE)              // contraction values per step
 #define NPL (KC / PE)             // cell planes per channel chunk
-#define NSTEP ((FW * KC + E - 1) / E)   // steps per filter row and chunk
+#define NTAPF (FW + S - 1)        // taps of one filter row with the column shifts
+#define NSTEP ((NTAPF * KC + E - 1) / E)   // steps per filter row and chunk
 #define NTAPS ((NSTEP * E) / KC)        // taps covered, padding included
 #define NCHUNK ((CIN + KC - 1) / KC)
 #define KSTEPS (FH * NSTEP)             // steps per chunk
@@ -100,12 +114,14 @@ static_assert(KC % PE == 0 && ((KC / PE) & (KC / PE - 1)) == 0, "KC must be PE t
 
 // ------------------------------------------------------------------ pack
 #ifdef FB_PACK_FRAG
-// One workgroup per column c of the packed bank (whole column blocks of the
-// correlation kernel; columns at or past COUT are zero).  Layout: 16-byte
-// cell ((j*NCHUNK + chunk)*KSTEPS2 + u*NSTEP + t)*64 + lane for column tile
-// j = c / MF, lane = MF*g + c%MF.  16-bit operands: e_c = floor(log2
-// max|w[c]|), values scaled by 2^-e_c (exact) and rounded to nearest even,
-// unscale[c] = 2^e_c (an all-zero filter gets e_c = 0).  FB_FLIP: the
+// One workgroup per column pc of the packed bank: whole column blocks of
+// the correlation kernel, NCOLW columns each, column (s, c) of a block
+// holding filter c shifted by s taps (columns of filters at or past COUT
+// are zero).  Layout: 16-byte cell ((j*NCHUNK + chunk)*KSTEPS2 + u*NSTEP +
+// t)*64 + lane for column tile j = pc / MF, lane = MF*g + pc%MF.  16-bit
+// operands: e_c = floor(log2 max|w[c]|), values scaled by 2^-e_c (exact)
+// and rounded to nearest even, unscale[pc] = 2^e_c (an all-zero filter gets
+// e_c = 0).  FB_FLIP: the
 // filters are those of the input-gradient correlation, read from the
 // forward bank w[CIN][FH][FW][COUT] flipped in (u, v) with the channel axes
 // exchanged.
@@ -119,8 +135,15 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
     constexpr int ITEMS = NCHUNK * FH * NTAPS * NPL;
     constexpr int PER = (ITEMS + 255) / 256;
     constexpr bool HELD = PER * PE <= 64;
-    const int c = blockIdx.x;
-    const int j = c / MF, col = c % MF;
+    const int pc = blockIdx.x;
+    const int j = pc / MF, col = pc % MF;
+#ifdef FB_NCOLW
+    // column (s, c) of its block
+    const int sh = (pc % FB_NCOLW) / (FB_NCOLW / S);
+    const int c = (pc / FB_NCOLW) * (FB_NCOLW / S) + (pc % FB_NCOLW) % (FB_NCOLW / S);
+#else
+    const int sh = 0, c = pc;
+#endif
     const bool real = c < COUT;
     auto load_item = [&](int e, float* vals) {
         const int p = e % NPL;
@@ -129,11 +152,12 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
         r /= NTAPS;
         const int u = r % FH, kci = r / FH;
         const int ch0 = kci * KC + p * PE;
-        const bool ok = e < ITEMS && real && vv < FW;
+        const int vf = vv - sh;                   // filter tap of this (shifted) column
+        const bool ok = e < ITEMS && real && vf >= 0 && vf < FW;
 #if !defined(FB_FLIP) && CIN % PE == 0
         // PE consecutive channels of one tap: contiguous in w[c][u][v][:]
         if (ok && ch0 < CIN) {
-            const float* src = w + (((long)c * FH + u) * FW + vv) * CIN + ch0;
+            const float* src = w + (((long)c * FH + u) * FW + vf) * CIN + ch0;
 #pragma unroll
             for (int q = 0; q < PE; q += 4) {
                 const rg_f32x4 x4 = *(const rg_f32x4*)(src + q);
@@ -148,9 +172,9 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
         for (int i = 0; i < PE; ++i) {
             const int ch = ch0 + i;
 #ifdef FB_FLIP
-            vals[i] = (ok && ch < CIN) ? w[(((long)ch * FH + (FH - 1 - u)) * FW + (FW - 1 - vv)) * COUT + c] : 0.f;
+            vals[i] = (ok && ch < CIN) ? w[(((long)ch * FH + (FH - 1 - u)) * FW + (FW - 1 - vf)) * COUT + c] : 0.f;
 #else
-            vals[i] = (ok && ch < CIN) ? w[(((long)c * FH + u) * FW + vv) * CIN + ch] : 0.f;
+            vals[i] = (ok && ch < CIN) ? w[(((long)c * FH + u) * FW + vf) * CIN + ch] : 0.f;
 #endif
         }
 #endif
@@ -218,7 +242,7 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
         ex -= 1;                  // floor(log2 m)
     }
     sc = ldexpf(1.0f, -ex);
-    if (threadIdx.x == 0) unscale[c] = real ? ldexpf(1.0f, ex) : 0.f;
+    if (threadIdx.x == 0) unscale[pc] = real ? ldexpf(1.0f, ex) : 0.f;
 #else
     (void)unscale;
     (void)m;
@@ -267,10 +291,11 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
 #define NREG (MF * MF / 64)           // accumulator registers per tile
 #define MC (MF / MR)                  // pixel columns of a tile
 #define TH (WM * MT * MR)             // output rows per workgroup
-#define TWO MC                        // output columns per workgroup
-#define CB (WN * NT * MF)             // filters per workgroup
+#define TWO (S * MC)                  // output columns per workgroup
+#define NCOLW (WN * NT * MF)          // matrix columns per workgroup
+#define CB (NCOLW / S)                // filters per workgroup
 #define TR (TH + FH - 1)              // tile rows
-#define TC (MC - 1 + NTAPS)           // tile columns any lane reads
+#define TC (S * (MC - 1) + NTAPS)     // tile columns any lane reads
 #define TCP (TC + XPADC)              // tile row stride in cells
 #define PLANE (TR * TCP)              // cells per plane
 #define TILE_CELLS (NPL * PLANE)
@@ -280,6 +305,7 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
 #define SB (SCELLS < (DT == 0 ? 16 : 8) ? SCELLS : (DT == 0 ? 16 : 8))
 
 static_assert(MF % MR == 0, "MR must divide MF");
+static_assert(NCOLW % S == 0, "the columns must split evenly into shifts");
 static_assert(PF >= 1, "ring depth");
 static_assert(CIN % PE == 0 || KC == PE, "partial cells need KC == PE");
 
@@ -390,11 +416,11 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
     const int lr = lane % MF, g = lane / MF;       // tile row (pixel) / lane group
     const int ti = lr / MC, tj = lr % MC;
     // this lane's first cell (step 0, filter row 0, pixel tile 0)
-    const int lb = RUN_PLANE(g * PE) * PLANE + (wm * MT * MR + ti) * TCP + tj + RUN_TAP(g * PE);
-    // this wave's first column tile; column tiles are NCHUNK*KSTEPS2
-    // kilobyte blocks apart (the packed bank has whole column blocks, so
-    // every tile a wave names exists)
-    const int j0 = c0 / MF + wn * NT;
+    const int lb = RUN_PLANE(g * PE) * PLANE + (wm * MT * MR + ti) * TCP + S * tj + RUN_TAP(g * PE);
+    // this wave's first column tile of the packed bank; column tiles are
+    // NCHUNK*KSTEPS2 kilobyte blocks apart (the bank has whole column
+    // blocks, so every tile a wave names exists)
+    const int j0 = cblk * (NCOLW / MF) + wn * NT;
     const rg_u32x4* bw = Bp + (long)j0 * NCHUNK * KSTEPS2 * 64 + lane;
 
     rg_acc acc[MT][NT];
@@ -529,9 +555,10 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
     auto store_all = [&](auto checked) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const int cc = c0 + (wn * NT + nt) * MF + lr;
+            const int col = (wn * NT + nt) * MF + lr;       // matrix column: (shift, filter)
+            const int sh = col / CB, cc = c0 + col % CB;
 #if DT != 0
-            const float us = (!decltype(checked)::value || cc < COUT) ? UNSCALE[cc] * ys : 0.f;   // exact: powers of two
+            const float us = (!decltype(checked)::value || cc < COUT) ? UNSCALE[cblk * NCOLW + col] * ys : 0.f;   // exact: powers of two
 #endif
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
@@ -543,7 +570,7 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
                     const int m = 4 * g + r;
 #endif
                     const int oi = oi0 + (wm * MT + mt) * MR + m / MC;
-                    const int oj = oj0 + m % MC;
+                    const int oj = oj0 + S * (m % MC) + sh;
                     if (!decltype(checked)::value || (oi < HO && oj < WO && cc < COUT)) {
 #if DT == 0
                         float val = acc[mt][nt][r];

@@ -154,6 +154,8 @@ def test_rgemm_knobs_accepted_and_checked():
                       ("forward", "algo=rgemm pf=9"),
                       ("forward", "algo=rgemm mt=8 nt=4 wpe=2"),  # accumulators over the register budget
                       ("forward", "algo=rgemm flip=1"),           # flip is the input gradient's
+                      ("forward", "algo=rgemm s=3"),
+                      ("forward", "algo=rgemm mf=16 nt=1 wn=1 s=32"),
                       ("backward_w", "algo=rgemm")]:
         with pytest.raises(FbcorrError):
             codegen(lp if role == "forward" else d, role, cfg)
@@ -246,6 +248,8 @@ def test_gpu_test_configurations_are_valid():
     d = fb.make_desc(2, 41, 67, 16, 64, 7, 7)
     for c in tr.DX_CFGS:
         fb.codegen(d, "backward_x", ("algo=rgemm " + c).strip())
+    for sh, prec, c in tr.SHIFT_SHAPES:
+        fb.codegen(fb.make_desc(*sh, precision=prec), "forward", "algo=rgemm " + c)
     for sh in tr.DX_SHAPES:
         fb.codegen(fb.make_desc(*sh), "backward_x", "algo=rgemm")
 

@@ -74,6 +74,10 @@ RGEMM_CFGS = [
     "kc=4 mr=8 mt=1 nt=1 wm=2 wn=2 pf=6",
     "kc=8 mr=2 mt=8 nt=1 wm=1 wn=2 pf=2 xcd=0",
     "kc=16 mr=2 mt=4 nt=2 wm=2 wn=2 pf=3",          # 128 columns for a 64-filter bank: half empty
+    # column shifts: 16 filters x 2 shifts, 8 filters x 4 shifts per block
+    "mf=32 s=2 kc=8 mr=2 mt=4 nt=1 wm=2 wn=1 pf=3",
+    "mf=16 s=4 kc=4 mr=1 mt=4 nt=1 wm=2 wn=2 pf=2",
+    "mf=16 s=2 kc=8 mr=2 mt=2 nt=2 wm=2 wn=1 pf=4 xpadc=1",
 ]
 
 
@@ -96,6 +100,8 @@ LOWP_CFGS = [
     "kc=16 mr=4 mt=4 nt=1 wm=2 wn=4 pf=4 xpadc=1",
     "kc=32 mr=2 mt=2 nt=2 wm=2 wn=2 pf=6 wpe=1",
     "kc=8 mr=2 mt=8 nt=1 wm=1 wn=2 pf=3",
+    "mf=32 s=2 kc=16 mr=2 mt=4 nt=2 wm=2 wn=1 pf=3",
+    "mf=16 s=4 kc=8 mr=1 mt=4 nt=1 wm=2 wn=2 pf=2",
 ]
 
 
@@ -175,6 +181,10 @@ DX_CFGS = [
     "mf=16 kc=8 mr=2 mt=4 nt=1 wm=2 wn=2 pf=2 xpadc=1",
     "mf=32 kc=16 mr=2 mt=4 nt=1 wm=2 wn=1 pf=3",
     "mf=16 kc=4 mr=4 mt=2 nt=1 wm=1 wn=1 pf=6 wpe=1",
+    # column shifts for the 16-channel input gradient
+    "mf=32 s=2 kc=16 mr=2 mt=4 nt=1 wm=2 wn=1 pf=3",
+    "mf=16 s=2 kc=16 mr=1 mt=8 nt=1 wm=4 wn=1 pf=3",
+    "mf=16 s=4 kc=8 mr=2 mt=2 nt=2 wm=2 wn=1 pf=4 xpadc=1",
 ]
 
 
@@ -217,3 +227,21 @@ def test_dx_random_fp32():
     sx, _ = oracle.backward_scales(x, w, g)
     e = oracle.normalised_error(_dx(s, x, w, g, ""), rx, sx)
     assert e[0] <= FP32_TOL, e
+
+
+SHIFT_SHAPES = [
+    # (shape, precision, configuration): banks narrower than a block
+    ((1, 60, 61, 16, 7, 5, 5), "fp32", "mf=16 s=2 kc=16 mr=2 mt=2 nt=1 wm=2 wn=2 pf=3"),
+    ((2, 37, 45, 3, 7, 3, 4), "fp32", "mf=32 s=4 kc=4 mr=2 mt=2 nt=1 wm=2 wn=1 pf=2"),
+    ((1, 64, 64, 4, 16, 5, 5), "bf16", "mf=32 s=2 kc=8 mr=2 mt=4 nt=1 wm=2 wn=1 pf=3"),
+    ((1, 50, 47, 8, 8, 9, 9), "fp16", "mf=16 s=2 kc=8 mr=1 mt=4 nt=1 wm=4 wn=1 pf=3"),
+]
+
+
+@pytest.mark.parametrize("shape,prec,cfg", SHIFT_SHAPES)
+def test_column_shift_integer_exact(shape, prec, cfg):
+    need_gpu()
+    s = wl.Shape(*shape)
+    x, w, _ = wl.draw_integer(s, seed=700 + sum(shape))
+    y = _run(_plan(s, prec, cfg), x, w)
+    np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
