@@ -479,11 +479,11 @@ static KernelSource util_source(const char* name, const char* define) {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// fp16 forward: the per-tensor input scale (reading c-10).  64 partial
+// fp16 forward: the per-tensor input scale (reading c-10).  256 partial
 // maxima of |x| from fbcorr_absmax, written after `ucount` unscale floats,
 // are combined by the correlation kernel (option FB_XMOFF).  Returns the
 // bytes of the unscale + partials region.
-static const int kInputMaxParts = 64;
+static const int kInputMaxParts = 256;
 static size_t add_input_scale(const fbcorr_desc& d, int dt, size_t ucount, RoleBuild& rb) {
     if (dt != 2) return align256(ucount * 4);
     const size_t xmoff = (ucount + 63) / 64 * 64;

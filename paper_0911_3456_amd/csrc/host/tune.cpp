@@ -40,7 +40,7 @@ static TuneLayout tune_layout(const Plan* p) {
     t.cand = off; off += align256(t.nout * 4);
     t.role_ws = off;
     // largest role workspace any candidate may ask for
-    size_t rw = std::max(align256(t.nw * 2) + align256((size_t)d.N * 4 + 512), align256(t.nw * 4));
+    size_t rw = std::max(align256(t.nw * 2) + align256((size_t)d.N * 4 + 2048), align256(t.nw * 4));
     rw = std::max(rw, align256(kMaxPartialsForTuning * t.nw * 4));
     // the fragment-ordered bank of the register-streamed forward kernel:
     // columns padded to at most 256, chunks of at least 4 channels, steps of
@@ -52,7 +52,7 @@ static TuneLayout tune_layout(const Plan* p) {
         const size_t cols = (size_t)(co + 255) / 256 * 256;
         const size_t chunks = (size_t)(ci + 3) / 4;
         const size_t steps = (size_t)d.fh * d.fw * (ci + 63) / 8 + chunks * d.fh + chunks * 8;
-        rw = std::max(rw, align256(cols * steps * 64) + align256(cols * 4 + 512));
+        rw = std::max(rw, align256(cols * steps * 64) + align256(cols * 4 + 2048));
     }
     off += rw;
     t.total = off;

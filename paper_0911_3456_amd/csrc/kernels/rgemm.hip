@@ -44,7 +44,7 @@
 //   problem  BATCH FH FW CIN COUT HI WI HO WO PADH PADW
 //   DT       0 fp32 operands, 1 bf16, 2 fp16 (B pre-scaled and rounded by
 //            the pack; UNSCALE[c] multiplies each output)
-//   XMOFF    fp16 only: UNSCALE[XMOFF .. XMOFF+63] hold partial maxima of |x|
+//   XMOFF    fp16 only: UNSCALE[XMOFF .. XMOFF+255] hold partial maxima of |x|
 //            (fbcorr_absmax); when the input reaches 2^15 it is scaled by
 //            2^-k while staged (max |x| * 2^-k < 2^15, inside the fp16
 //            range) and the outputs by 2^k -- both exact powers of two
@@ -317,11 +317,12 @@ typedef rg_f32x16 rg_acc;
 typedef rg_f32x4 rg_acc;
 #endif
 
-// fp16 input scale exponent k >= 0 from the 64 partial maxima of |x| (one
+// fp16 input scale exponent k >= 0 from the 256 partial maxima of |x| (four
 // per lane of the wave, combined by shuffles; the same in every lane).
 __device__ __forceinline__ int rg_input_scale_exp(const float* __restrict__ UNSCALE) {
 #if DT == 2 && defined(FB_XMOFF)
-    float m = UNSCALE[FB_XMOFF + (threadIdx.x & 63)];
+    const float* pm = UNSCALE + FB_XMOFF + 4 * (threadIdx.x & 63);
+    float m = fmaxf(fmaxf(pm[0], pm[1]), fmaxf(pm[2], pm[3]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     int e = 0;

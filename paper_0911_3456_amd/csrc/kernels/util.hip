@@ -13,7 +13,7 @@
 //                        bf16 (LOWP=1) or fp16 (LOWP=2), unscale[n] = 2^e_n
 //                        (an all-zero filter gets e_n = 0).
 //   fbcorr_absmax        part[g] = max |x[i]| over workgroup g's share of the
-//                        n input values (NXP workgroups): the fp16 forward's
+//                        n input values (256 workgroups): the fp16 forward's
 //                        per-tensor input scale is derived from these.
 //   fbcorr_fill_int      integer-valued pattern in [-R, R] (tuner gate data).
 //   fbcorr_transpose_filters  wt[((u*FW + v)*D + d)*NPAD + n] = w[n,u,v,d]
@@ -182,11 +182,22 @@ typedef float f32x4a __attribute__((ext_vector_type(4)));
 extern "C" __global__ void __launch_bounds__(256)
 fbcorr_absmax(const float* __restrict__ x, long n, float* __restrict__ part)
 {
-    // 16-byte loads where the data allows, then the scalar tail
+    // 16-byte loads where the data allows, four in flight per thread, then
+    // the scalar tail
     __shared__ float red[4];
     float m = 0.f;
     const long n4 = (((unsigned long)x & 15) == 0) ? n / 4 : 0;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long)gridDim.x * 256) {
+    const long stride = (long)gridDim.x * 256;
+    long i = (long)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        f32x4a v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = ((const f32x4a*)x)[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(v[k][0]), fabsf(v[k][1])), fmaxf(fabsf(v[k][2]), fabsf(v[k][3]))));
+    }
+    for (; i < n4; i += stride) {
         const f32x4a v = ((const f32x4a*)x)[i];
         m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
     }
