@@ -26,8 +26,9 @@ Also printed in the same JSON line:
   direct_fp32   the plain fp32 direct kernel (vector ALU, auto-tuned) on that
                 shape's forward pass, against the 157.3 TFLOP/s fp32 vector
                 peak.
-  precision     the 512x512x16 / 128x13x13x16 forward: fp32 direct, fp32
-                matrix-core, bf16 and fp16 matrix-core times, the bf16/fp16
+  precision     the 512x512x16 / 128x13x13x16 forward: fp32 direct
+                (fp32_direct), fp32, bf16 and fp16 on the matrix cores
+                (fp32_mfma, bf16_mfma, fp16_mfma) times, the bf16/fp16
                 speedups over the fp32 direct kernel, and each one's
                 normalised error against FP64 oracle values stored at 132
                 sites x 128 filters (tests/golden/precision_sites.npz, written
@@ -126,6 +127,8 @@ TRAFFIC_FILES = {
     TABLE_WORKLOAD: "traffic_fp32_256x256x8_64x9x9x8.txt",
     "nn": "traffic_nn_4096x1048576x64.txt",
     "batched": "traffic_batched_256.txt",
+    "precision_bf16": "traffic_bf16_512x512x16_128x13x13x16.txt",
+    "precision_fp16": "traffic_fp16_512x512x16_128x13x13x16.txt",
 }
 
 
@@ -148,10 +151,10 @@ COPY_BYTES = 256 << 20
 
 def traffic_probe():
     """For counter runs (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE): the step
-    workloads' kernels three times each, the batched launch and the
-    nearest-neighbour search, plus a device copy of COPY_BYTES whose
-    counter readings calibrate the counters (it moves COPY_BYTES in and
-    COPY_BYTES out)."""
+    workloads' kernels three times each, the 16-bit forwards of the precision
+    workload, the batched launch and the nearest-neighbour search, plus a
+    device copy of COPY_BYTES after each execution whose counter readings
+    calibrate the counters (it moves COPY_BYTES in and COPY_BYTES out)."""
     import torch
     import workloads as wl
     from paper_0911_3456_amd import BatchedPlan, NNPlan, Plan
@@ -175,6 +178,21 @@ def traffic_probe():
         for r in ROLES:
             print(name, r, kernel_fingerprint(plan, r), plan.get_config(r), flush=True)
         plan.close()
+    wk = wl.WORKLOADS["precision"]
+    s = wk.shape
+    x, w, _ = wl.draw_single(s, wk.seed)
+    xt, wt = torch.from_numpy(x).to(dev), torch.from_numpy(w).to(dev)
+    for prec in ("bf16", "fp16"):
+        plan = Plan(s.batch, s.H, s.W, s.D, s.N, s.fh, s.fw, precision=prec, device=dev)
+        y = torch.empty(plan.y_shape, device=dev)
+        for _ in range(3):
+            plan.forward(xt, wt, y)
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("precision_" + prec, "forward", kernel_fingerprint(plan, "forward"), plan.get_config("forward"),
+              flush=True)
+        plan.close()
+    del xt, wt
     shapes, xs, fs = wl.draw_batched()
     bplan = BatchedPlan([(s.H, s.W, s.D, s.N, s.fh, s.fw) for s in shapes], device=dev)
     xd = [torch.from_numpy(v).to(dev) for v in xs]
@@ -411,19 +429,24 @@ def precision_leg(steps: int, warmup: int, use_graph: bool = True):
                                                  "j": int(ref["sites"][arg[0], 1]), "n": int(arg[1])},
                                       "outputs_compared": int(err.size)}}
         if algo == "igemm" and prec != "fp32":
+            fp = kernel_fingerprint(plan, "forward")
             row["roofline"] = {"bound": "mfma", "achieved": row["tflops"], "peak": BF16_MATRIX_PEAK_TFLOPS,
-                               "unit": "TFLOP/s", "frac": round(row["tflops"] / BF16_MATRIX_PEAK_TFLOPS, 4)}
+                               "unit": "TFLOP/s", "frac": round(row["tflops"] / BF16_MATRIX_PEAK_TFLOPS, 4),
+                               "traffic": load_traffic("forward", fp, TRAFFIC_FILES["precision_" + prec]),
+                               "fingerprint": fp}
         elif algo == "igemm":
             row["roofline"] = {"bound": "mfma", "achieved": row["tflops"], "peak": FP32_MATRIX_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": round(row["tflops"] / FP32_MATRIX_PEAK_TFLOPS, 4)}
         else:
             row["roofline"] = {"bound": "alu", "achieved": row["tflops"], "peak": FP32_VECTOR_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": round(row["tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4)}
-        out["%s_%s" % (prec, algo)] = row
+        # "mfma": the plan's matrix-core kernel (the database's choice of the
+        # LDS-staged or the register-streamed implicit GEMM, named in "config")
+        out["%s_%s" % (prec, "mfma" if algo == "igemm" else algo)] = row
         torch.cuda.synchronize()
         plan.close()
     base = out["fp32_direct"]["ms"]
-    for k in ("fp32_igemm", "bf16_igemm", "fp16_igemm"):
+    for k in ("fp32_mfma", "bf16_mfma", "fp16_mfma"):
         out[k]["speedup_vs_fp32_direct"] = round(base / out[k]["ms"], 3)
     out["err_tolerance"] = {"fp32": 1e-5, "bf16": 1e-2, "fp16": 1e-2}
     out["err_metric"] = ("|y - y_fp64| / sum |x||w| over each output's terms, at 132 sites x 128 filters "
