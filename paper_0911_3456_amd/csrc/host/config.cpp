@@ -319,7 +319,10 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     const int ncolw = wn * nt * mf, cb = ncolw / sh;
     const int th = wm * mt * mr, two = sh * mc;
     const int tr = th + fh - 1, tc = sh * (mc - 1) + ntaps, tcp = tc + xpadc;
-    const long lds = (long)npl * tr * tcp * 16;
+    const int ste = c.get("ste");
+    if (ste && (sh != 1 || cout % 4)) { err = "rgemm: ste needs s=1 and a multiple of 4 output channels"; return false; }
+    long lds = (long)npl * tr * tcp * 16;
+    if (ste) lds = std::max(lds, (long)wm * wn * mf * (nt * mf + 8) * 4);
     if (lds > di.lds_per_block) { err = "rgemm: LDS " + std::to_string(lds) + " B exceeds the device limit"; return false; }
     const int ho = hi + 2 * padh - fh + 1, wo = wi + 2 * padw - fw + 1;
     const long grid = (long)cdiv(wo, two) * cdiv(ho, th) * cdiv(cout, cb) * batch;
@@ -348,6 +351,7 @@ static bool geom_rgemm(const char* kname, const Config& c, int batch, int hi, in
     opt(ks.options, "XPADC", xpadc); opt(ks.options, "WPE", wpe); opt(ks.options, "XCDMAP", xcd ? 1 : 0);
     if (unr) opt(ks.options, "UNR", 1);
     if (c.get("nts")) opt(ks.options, "NTS", 1);
+    if (ste) opt(ks.options, "STE", 1);
     pack = KernelSource();
     pack.name = "fbcorr_pack_frag";
     pack.file = "rgemm";
@@ -514,7 +518,8 @@ static bool known_keys(const Config& c, std::string& err) {
                    "uunr", "swz"}},
         {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
-        {"rgemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip", "nts"}},
+        {"rgemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip", "nts",
+                   "ste"}},
     };
     auto it = keys.find(c.algo);
     if (it == keys.end()) { err = "unknown algorithm '" + c.algo + "'"; return false; }

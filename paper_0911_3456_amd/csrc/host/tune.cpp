@@ -165,9 +165,12 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                         for (int pf : {2, 3, 4, 6})
                             for (int xp : {0, 1})
                                 for (int wpe : {1, 2})
-                                  for (int nts : {0, 1}) {
+                                  for (int nts : {0, 1})
+                                   for (int ste : {0, 1}) {
                                     Config c = rb;
                                     c.v["nts"] = nts;
+                                    if (ste && (sv != 1 || cout % 4)) continue;
+                                    c.v["ste"] = ste;
                                     if (sh[1] * sh[3] * mf > std::max(mf, ((cout * sv + mf - 1) / mf) * mf)) continue;
                                     if (mf == 16 && cout > 64) continue;
                                     if (sv > 1 && (sh[1] * sh[3] * mf) % sv) continue;

@@ -55,7 +55,8 @@
 //            XPADC (LDS row padding in cells), WPE (waves per SIMD the
 //            register budget is sized for), UNR (1: unroll the step loop
 //            completely), XCDMAP (XCD-aware workgroup order), NTS (1:
-//            non-temporal output stores)
+//            non-temporal output stores), STE (1: interior tiles store
+//            through LDS as 16-byte vectors)
 //   naming   KNAME   EPILOGUE(v, c) as in the LDS-staged kernel
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
@@ -300,12 +301,26 @@ fbcorr_pack_frag(const float* __restrict__ w, rg_u32x4* __restrict__ bp, float* 
 #define PLANE (TR * TCP)              // cells per plane
 #define TILE_CELLS (NPL * PLANE)
 #define NTHREADS (WM * WN * 64)
+#if defined(FB_STE) && FB_STE
+// Stores through LDS: per wave, one pixel tile's worth of its columns as
+// rows of NT*MF floats (+8: the two lane groups' rows land on different
+// banks), read back as 16-byte vectors
+#define STE 1
+#define SROW (NT * MF + 8)
+#define SWAVE (MF * SROW)
+#define STE_CELLS ((WM * WN * SWAVE + 3) / 4)
+#define LDS_CELLS (TILE_CELLS > STE_CELLS ? TILE_CELLS : STE_CELLS)
+#else
+#define STE 0
+#define LDS_CELLS TILE_CELLS
+#endif
 // tile cells staged per thread and batch (all of them when they are few)
 #define SCELLS ((NPL * TR * TC + NTHREADS - 1) / NTHREADS)
 #define SB (SCELLS < (DT == 0 ? 16 : 8) ? SCELLS : (DT == 0 ? 16 : 8))
 
 static_assert(MF % MR == 0, "MR must divide MF");
 static_assert(NCOLW % S == 0, "the columns must split evenly into shifts");
+static_assert(!STE || S == 1, "stores through LDS need unshifted columns");
 static_assert(PF >= 1, "ring depth");
 static_assert(CIN % PE == 0 || KC == PE, "partial cells need KC == PE");
 
@@ -389,7 +404,7 @@ extern "C" __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_wav
 FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const float* __restrict__ UNSCALE,
          float* __restrict__ O)
 {
-    __shared__ rg_u32x4 tile[TILE_CELLS];
+    __shared__ rg_u32x4 tile[LDS_CELLS];
 
     // Workgroup -> (image, column block, tile row, tile column); with XCDMAP
     // each XCD gets a contiguous range (shared halos stay in its L2).
@@ -597,7 +612,62 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
             }
         }
     };
+#if STE
+    if (interior) {
+        // Stores through LDS: each pixel tile of the wave's columns goes to
+        // the wave's own LDS rows (the input tile is dead once every wave is
+        // past its last step) and back out as 16-byte vectors, so that one
+        // store instruction writes whole runs of a pixel's channels.
+        __syncthreads();
+        float* const sbuf = (float*)tile + wave * SWAVE;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int col = (wn * NT + nt) * MF + lr;
+#if DT != 0
+                const float us = UNSCALE[cblk * NCOLW + col] * ys;      // exact: powers of two
+#endif
+#pragma unroll
+                for (int r = 0; r < NREG; ++r) {
+#if MF == 32
+                    const int m = 8 * (r >> 2) + 4 * g + (r & 3);
+#else
+                    const int m = 4 * g + r;
+#endif
+#if DT == 0
+                    float val = acc[mt][nt][r];
+#else
+                    float val = acc[mt][nt][r] * us;
+#endif
+#ifdef FB_EPILOGUE
+                    val = FB_EPILOGUE(val, c0 + col);
+#endif
+                    sbuf[m * SROW + nt * MF + lr] = val;
+                }
+            }
+            // MF rows of NT*MF/4 vectors, 64 per instruction
+#pragma unroll
+            for (int it = lane; it < MF * NT * MF / 4; it += 64) {
+                const int m = it / (NT * MF / 4), c4 = it % (NT * MF / 4);
+                const rg_f32x4 v = *(const rg_f32x4*)(sbuf + m * SROW + c4 * 4);
+                const int oi = oi0 + (wm * MT + mt) * MR + m / MC;
+                const int oj = oj0 + m % MC;
+                rg_f32x4* const dst =
+                    (rg_f32x4*)(Ob + (unsigned)((oi * WO + oj) * COUT + c0 + wn * NT * MF + c4 * 4));
+#if defined(FB_NTS) && FB_NTS
+                __builtin_nontemporal_store(v, dst);
+#else
+                *dst = v;
+#endif
+            }
+        }
+    } else {
+        store_all(RgBool<true>{});
+    }
+#else
     if (interior) store_all(RgBool<false>{});
     else store_all(RgBool<true>{});
+#endif
 }
 #endif  // !FB_PACK_FRAG

@@ -78,6 +78,10 @@ RGEMM_CFGS = [
     "mf=32 s=2 kc=8 mr=2 mt=4 nt=1 wm=2 wn=1 pf=3",
     "mf=16 s=4 kc=4 mr=1 mt=4 nt=1 wm=2 wn=2 pf=2",
     "mf=16 s=2 kc=8 mr=2 mt=2 nt=2 wm=2 wn=1 pf=4 xpadc=1",
+    # interior tiles stored through LDS as 16-byte vectors (edge tiles as before)
+    "kc=8 mr=2 mt=4 nt=2 wm=2 wn=1 pf=3 ste=1",
+    "mf=16 kc=8 mr=1 mt=4 nt=2 wm=2 wn=2 pf=2 ste=1 nts=1",
+    "kc=16 mr=4 mt=2 nt=1 wm=2 wn=2 pf=3 ste=1",
 ]
 
 
@@ -102,6 +106,8 @@ LOWP_CFGS = [
     "kc=8 mr=2 mt=8 nt=1 wm=1 wn=2 pf=3",
     "mf=32 s=2 kc=16 mr=2 mt=4 nt=2 wm=2 wn=1 pf=3",
     "mf=16 s=4 kc=8 mr=1 mt=4 nt=1 wm=2 wn=2 pf=2",
+    "kc=16 mr=2 mt=4 nt=2 wm=2 wn=2 pf=3 ste=1",
+    "kc=16 mr=1 mt=8 nt=1 wm=1 wn=4 pf=4 ste=1 nts=1",
 ]
 
 
@@ -185,6 +191,7 @@ DX_CFGS = [
     "mf=32 s=2 kc=16 mr=2 mt=4 nt=1 wm=2 wn=1 pf=3",
     "mf=16 s=2 kc=16 mr=1 mt=8 nt=1 wm=4 wn=1 pf=3",
     "mf=16 s=4 kc=8 mr=2 mt=2 nt=2 wm=2 wn=1 pf=4 xpadc=1",
+    "mf=16 kc=16 mr=1 mt=8 nt=1 wm=4 wn=1 pf=3 ste=1",
 ]
 
 
@@ -245,3 +252,16 @@ def test_column_shift_integer_exact(shape, prec, cfg):
     x, w, _ = wl.draw_integer(s, seed=700 + sum(shape))
     y = _run(_plan(s, prec, cfg), x, w)
     np.testing.assert_array_equal(y, oracle.forward(x, w).astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_stores_through_lds_with_epilogue(prec):
+    """A fused epilogue (clamp to [0, 2]) on the LDS-transposed stores of
+    interior tiles and the direct stores of edge tiles: exact on integers."""
+    need_gpu()
+    s = wl.Shape(1, 53, 70, 16, 64, 5, 5)
+    x, w, _ = wl.draw_integer(s, seed=81, xmax=2, wmax=2)
+    plan = _plan(s, prec, "kc=16 mr=2 mt=2 nt=2 wm=2 wn=1 pf=3 ste=1")
+    plan.set_epilogue("fminf(fmaxf(v, 0.f), 2.f)")
+    y = _run(plan, x, w)
+    np.testing.assert_array_equal(y, np.clip(oracle.forward(x, w), 0, 2).astype(np.float32))
