@@ -152,7 +152,10 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                 if (k <= std::max(cin, 2 * pe) && (cin % pe == 0)) rkcs.push_back(k);
             const int rshapes[][4] = {{4, 2, 2, 2}, {4, 2, 1, 2}, {4, 2, 4, 1}, {2, 2, 2, 2}, {2, 2, 4, 2},
                                       {4, 1, 2, 4}, {4, 1, 4, 2}, {8, 1, 2, 2}, {2, 4, 2, 1}, {4, 2, 2, 1},
-                                      {2, 2, 4, 1}, {4, 1, 4, 1}, {4, 4, 1, 2}, {2, 1, 4, 2}, {8, 1, 1, 4}};
+                                      {2, 2, 4, 1}, {4, 1, 4, 1}, {4, 4, 1, 2}, {2, 1, 4, 2}, {8, 1, 1, 4},
+                                      // 16 tiles per wave: one wave per SIMD (wpe=1), half the
+                                      // fragment loads per product of the 8-tile shapes
+                                      {4, 4, 2, 1}, {4, 4, 4, 1}, {8, 2, 1, 2}, {8, 2, 2, 2}};
             // column shifts for banks narrower than a tile
             std::vector<int> rss = {1};
             for (int sv : {2, 4})

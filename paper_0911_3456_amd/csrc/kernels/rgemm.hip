@@ -20,8 +20,11 @@
 // * The input tile of a channel chunk (with its FH-1 / FW-1 halo) is staged
 //   once in LDS as 16-byte cells of PE consecutive channels, NPL = KC/PE
 //   planes of cells.  The 16 lanes that read together take 16 consecutive
-//   pixel columns of one plane: 256 contiguous bytes, free of bank
-//   conflicts for any row stride.
+//   pixel columns of one plane: 256 contiguous bytes.  (gfx950 also pairs
+//   lanes l and l+16 of each half-wave: their two 256-byte runs cost no
+//   extra cycle only when they start at the same offset modulo 256 bytes,
+//   i.e. when the row stride TCP is a multiple of 16 cells for MC = 16;
+//   XPADC sets the stride.)
 //
 // Contraction order.  Within a filter row u and chunk, the run of (v, k)
 // pairs (tap-major, FW*KC values, zero-padded to NSTEP*E) is cut into steps
