@@ -156,9 +156,16 @@ def test_rgemm_knobs_accepted_and_checked():
                       ("forward", "algo=rgemm flip=1"),           # flip is the input gradient's
                       ("forward", "algo=rgemm s=3"),
                       ("forward", "algo=rgemm mf=16 nt=1 wn=1 s=32"),
+                      ("forward", "algo=rgemm mf=32 s=2 mt=4 nt=1 wm=2 wn=1 ste=1"),   # ste needs s=1
                       ("backward_w", "algo=rgemm")]:
         with pytest.raises(FbcorrError):
             codegen(lp if role == "forward" else d, role, cfg)
+    # stores through LDS and streaming stores reach the options; ste needs a
+    # multiple of 4 output channels (16-byte rows)
+    _, o = codegen(lp, "forward", "algo=rgemm mf=32 kc=16 mr=2 mt=4 nt=2 wm=2 wn=2 pf=3 ste=1 nts=1")
+    assert "-DFB_STE=1" in o and "-DFB_NTS=1" in o
+    with pytest.raises(FbcorrError):
+        codegen(make_desc(1, 40, 40, 8, 30, 5, 5), "forward", "algo=rgemm mf=32 mt=2 nt=1 wm=2 wn=1 ste=1")
 
 
 def test_fp16_forward_has_input_scale():
