@@ -616,11 +616,13 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
         }
     };
 #if STE
-    if (interior) {
+    if (c0 + CB <= COUT) {
         // Stores through LDS: each pixel tile of the wave's columns goes to
         // the wave's own LDS rows (the input tile is dead once every wave is
         // past its last step) and back out as 16-byte vectors, so that one
-        // store instruction writes whole runs of a pixel's channels.
+        // store instruction writes whole runs of a pixel's channels.  Every
+        // channel of the column block exists (COUT is a multiple of 4);
+        // pixels past the image edge are skipped per vector.
         __syncthreads();
         float* const sbuf = (float*)tile + wave * SWAVE;
 #pragma unroll
@@ -658,11 +660,13 @@ FB_KNAME(const float* __restrict__ I, const rg_u32x4* __restrict__ Bp, const flo
                 const int oj = oj0 + m % MC;
                 rg_f32x4* const dst =
                     (rg_f32x4*)(Ob + (unsigned)((oi * WO + oj) * COUT + c0 + wn * NT * MF + c4 * 4));
+                if (interior || (oi < HO && oj < WO)) {
 #if defined(FB_NTS) && FB_NTS
-                __builtin_nontemporal_store(v, dst);
+                    __builtin_nontemporal_store(v, dst);
 #else
-                *dst = v;
+                    *dst = v;
 #endif
+                }
             }
         }
     } else {
