@@ -107,6 +107,7 @@ LOWP_CFGS = [
     "mf=32 s=2 kc=16 mr=2 mt=4 nt=2 wm=2 wn=1 pf=3",
     "mf=16 s=4 kc=8 mr=1 mt=4 nt=1 wm=2 wn=2 pf=2",
     "kc=16 mr=2 mt=4 nt=2 wm=2 wn=2 pf=3 ste=1",
+    "kc=16 mr=4 mt=4 nt=2 wm=2 wn=2 pf=4 ste=1 nts=1",
     "kc=16 mr=1 mt=8 nt=1 wm=1 wn=4 pf=4 ste=1 nts=1",
     # one wave per SIMD with 16 accumulator tiles (accumulators in AGPRs)
     "kc=16 mr=2 mt=4 nt=4 wm=2 wn=1 pf=3 wpe=1 ste=1",
