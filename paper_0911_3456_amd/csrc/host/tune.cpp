@@ -224,12 +224,17 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
         const Config base = default_config(d, role, DeviceInfo{"gfx950", 256, 160 * 1024, 1024});
         const int tiles = ((d.N + 31) / 32) * ((d.fh * d.fw * d.D + 31) / 32);
         std::vector<Config> grid;
-        // chunk widths: powers of two, and the divisors of the output width
-        // that leave no ragged chunk column
+        // chunk widths: powers of two, and the widths that cut the output
+        // width into k nearly equal chunks (exactly when k divides it), so
+        // the last chunk column carries little or no padding
         std::vector<int> rws = {32, 64};
         const int wo = d.W - d.fw + 1;
-        for (int k = 1; k <= 16; ++k)
-            if (wo % k == 0 && wo / k >= 16 && wo / k <= 128 && wo / k != 32 && wo / k != 64) rws.push_back(wo / k);
+        for (int k = 1; k <= 16; ++k) {
+            const int rw = (wo + k - 1) / k;
+            if (rw >= 16 && rw <= 128 && k * rw - wo < k &&
+                std::find(rws.begin(), rws.end(), rw) == rws.end())
+                rws.push_back(rw);
+        }
         const int ho = d.H - d.fh + 1;
         for (int rh : {1, 2, 4})
             for (int rw : rws) {
