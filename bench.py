@@ -47,6 +47,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import subprocess
@@ -101,25 +102,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _code_only(src: str) -> str:
+    """Kernel source without its comments, so that a comment edit does not
+    orphan the counter summaries taken on unchanged code."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.sub(r"//[^\n]*", "", src)
+
+
 def kernel_fingerprint(plan, role: str) -> str:
-    """Hash of the generated source and options of a role's main kernel."""
+    """Hash of the generated source (comments aside) and options of a role's
+    main kernel."""
     import paper_0911_3456_amd as fb
     cfg = plan.get_config(role).split(" (")[0]
     src, opts = fb.codegen(plan.desc, role, cfg)
-    return hashlib.sha256((src + "\0" + opts).encode()).hexdigest()[:16]
+    return hashlib.sha256((_code_only(src) + "\0" + opts).encode()).hexdigest()[:16]
 
 
 def nn_fingerprint(plan) -> str:
-    """Hash of the nearest-neighbour kernel template, configuration and shape."""
+    """Hash of the nearest-neighbour kernel template (comments aside),
+    configuration and shape."""
     src = open(os.path.join(ROOT, "paper_0911_3456_amd", "csrc", "kernels", "nn.hip")).read()
-    return hashlib.sha256((src + "\0" + plan.get_config() + "\0" + repr(plan.shape)).encode()).hexdigest()[:16]
+    return hashlib.sha256((_code_only(src) + "\0" + plan.get_config() + "\0" + repr(plan.shape)).encode()).hexdigest()[:16]
 
 
 def batched_fingerprint(plan) -> str:
     """Hash of the batched plan's configuration (every variant) and the
-    igemm template its kernel is generated from."""
+    igemm template its kernel is generated from (comments aside)."""
     src = open(os.path.join(ROOT, "paper_0911_3456_amd", "csrc", "kernels", "igemm.hip")).read()
-    return hashlib.sha256((src + "\0" + plan.describe()).encode()).hexdigest()[:16]
+    return hashlib.sha256((_code_only(src) + "\0" + plan.describe()).encode()).hexdigest()[:16]
 
 
 TRAFFIC_FILES = {

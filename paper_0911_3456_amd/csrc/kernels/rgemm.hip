@@ -52,14 +52,15 @@
 //            2^-k while staged (max |x| * 2^-k < 2^15, inside the fp16
 //            range) and the outputs by 2^k -- both exact powers of two
 //   tiling   MF (32 or 16: MFMA tile), KC (channels per chunk: PE times a
-//            power of two), S (column shift, below), MR (rows of an
+//            power of two), S (column shift, above), MR (rows of an
 //            MF-pixel tile), MT NT (tiles per
 //            wave), WM WN (waves), PF (filter-fragment ring depth in steps),
 //            XPADC (LDS row padding in cells), WPE (waves per SIMD the
 //            register budget is sized for), UNR (1: unroll the step loop
 //            completely), XCDMAP (XCD-aware workgroup order), NTS (1:
-//            non-temporal output stores), STE (1: interior tiles store
-//            through LDS as 16-byte vectors)
+//            non-temporal output stores), STE (1: tiles of whole column
+//            blocks store through LDS as 16-byte vectors, pixels past the
+//            image edge skipped)
 //   naming   KNAME   EPILOGUE(v, c) as in the LDS-staged kernel
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
