@@ -369,11 +369,12 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
                         KernelSource& ks, std::string& err) {
     const int th = c.get("th"), tw = c.get("tw"), p = c.get("p"), q = c.get("q"), nb = c.get("nb");
     const int ds = c.get("ds"), layout = c.get("layout"), xpad = c.get("xpad"), wpad = c.get("wpad");
-    const int ud = c.get("ud"), xcd = c.get("xcd"), fsrc = c.get("fsrc");
+    const int ud = c.get("ud"), xcd = c.get("xcd"), fsrc = c.get("fsrc"), sb = c.get("sb");
     if (th < 1 || tw < 1 || p < 1 || q < 1 || nb < 1 || ds < 1 || xpad < 0 || wpad < 0 || ud < 1) {
         err = "direct: every knob must be positive"; return false;
     }
     if (fsrc != 0 && fsrc != 1) { err = "direct: fsrc is 0 or 1"; return false; }
+    if (sb != 0 && sb != 1) { err = "direct: sb is 0 or 1"; return false; }
     if (fsrc && (ds != 1 || (th * (tw / p)) % 64 != 0)) {
         err = "direct: scalar weights (fsrc=1) need ds=1 and th*tw/p a multiple of 64"; return false;
     }
@@ -409,6 +410,7 @@ static bool geom_direct(const Config& c, const fbcorr_desc& d, const DeviceInfo&
     opt(ks.options, "NB", nb); opt(ks.options, "DS", ds); opt(ks.options, "LAYOUT", layout);
     opt(ks.options, "XPAD", xpad); opt(ks.options, "WPAD", wpad); opt(ks.options, "UD", ud);
     opt(ks.options, "XCDMAP", xcd ? 1 : 0);
+    if (sb) opt(ks.options, "SB", 1);
     if (fsrc) {
         opt(ks.options, "FSRC", 1);
         opt(ks.options, "NPAD", cdiv(d.N, nb) * nb);
@@ -516,7 +518,7 @@ static bool known_keys(const Config& c, std::string& err) {
     static const std::map<std::string, std::vector<std::string>> keys = {
         {"igemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "ks", "xpad", "wpad", "ustage", "xcd", "flip",
                    "uunr", "swz"}},
-        {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc"}},
+        {"direct", {"th", "tw", "p", "q", "nb", "ds", "layout", "xpad", "wpad", "ud", "xcd", "fsrc", "sb"}},
         {"dw", {"rh", "rw", "nw", "tpb", "np", "gpad", "xpad", "pf", "bal", "unr", "skipe"}},
         {"rgemm", {"mf", "kc", "s", "mr", "mt", "nt", "wm", "wn", "pf", "xpadc", "wpe", "unr", "xcd", "flip", "nts",
                    "ste"}},

@@ -28,6 +28,8 @@
 //            XCDMAP (XCD-aware workgroup order)
 //            FSRC (filter source: 0 LDS slice, 1 scalar loads; NPAD = filter
 //            count of the tap-major copy)
+//            SB (1: the input tile and each filter slice are staged with
+//            every load of a batch issued before the first store)
 //   EPILOGUE(v, c)  optional elementwise function of an output value v and
 //            its filter c, applied before the store (a fused nonlinearity)
 #ifndef __HIPCC_RTC__
@@ -63,6 +65,11 @@
 #else
 #define FSRC 0
 #endif
+#ifdef FB_SB
+#define SB FB_SB              // 1: staging loads issued in batches (see below)
+#else
+#define SB 0
+#endif
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -82,6 +89,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #endif
 #define NBS (NB + WPAD)
 #define WSL_ELEMS (FW * D * NBS)
+#define WIT ((NB * FW * D + NTHREADS - 1) / NTHREADS)   // filter-slice values per thread
 
 static_assert(TW % P == 0, "P must divide TW");
 static_assert(NB % Q == 0, "Q must divide NB");
@@ -128,7 +136,39 @@ fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* _
     // Stage the input tile; outside the image stays zero (only reachable by
     // outputs that are not stored).
     const long xb = (long)b * H * W * D;
-#if D % 4 == 0
+#if D % 4 == 0 && SB
+    // In batches of XB 16-byte loads per thread, every load of a batch
+    // issued before the first store (one memory latency per batch).
+    {
+        constexpr int XIT = (TRR * TCC * D + NTHREADS * 4 - 1) / (NTHREADS * 4);
+        constexpr int XB = XIT < 6 ? XIT : 6;
+#pragma unroll 1
+        for (int i0 = 0; i0 < XIT; i0 += XB) {
+            f32x4 v[XB];
+#pragma unroll
+            for (int i = 0; i < XB; ++i) {
+                const int e = (tid + (i0 + i) * NTHREADS) * 4;
+                const int r = e / (TCC * D), rem = e % (TCC * D);
+                const int c = rem / D, d = rem % D;
+                const int ii = oi0 + r, jj = oj0 + c;
+                v[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                if (e < TRR * TCC * D && ii < H && jj < W) v[i] = *(const f32x4*)(x + xb + ((long)ii * W + jj) * D + d);
+            }
+#pragma unroll
+            for (int i = 0; i < XB; ++i) {
+                const int e = (tid + (i0 + i) * NTHREADS) * 4;
+                const int r = e / (TCC * D), rem = e % (TCC * D);
+                const int c = rem / D, d = rem % D;
+                if (e < TRR * TCC * D) {
+                    tile[TIDX(d, r, c)] = v[i][0];
+                    tile[TIDX(d + 1, r, c)] = v[i][1];
+                    tile[TIDX(d + 2, r, c)] = v[i][2];
+                    tile[TIDX(d + 3, r, c)] = v[i][3];
+                }
+            }
+        }
+    }
+#elif D % 4 == 0
     for (int e = tid * 4; e < TRR * TCC * D; e += NTHREADS * 4) {
         const int r = e / (TCC * D), rem = e % (TCC * D);
         const int c = rem / D, d = rem % D;
@@ -168,12 +208,31 @@ fbcorr_direct(const float* __restrict__ x, const float* __restrict__ w, float* _
 #if !FSRC
         __syncthreads();
         // Filter slice for row u, stored [v][d][filter] so that the Q weights
-        // of one tap are contiguous.
+        // of one tap are contiguous; every load issued before the first store.
+#if SB && WIT <= 32
+        {
+            float wv[WIT];
+#pragma unroll
+            for (int k = 0; k < WIT; ++k) {
+                const int e = tid + k * NTHREADS;
+                const int f = e / (FW * D), vd = e % (FW * D);
+                const int n = n0 + f;
+                wv[k] = (e < NB * FW * D && n < N) ? w[((long)n * FH + u) * FW * D + vd] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < WIT; ++k) {
+                const int e = tid + k * NTHREADS;
+                const int f = e / (FW * D), vd = e % (FW * D);
+                if (e < NB * FW * D) wsl[vd * NBS + f] = wv[k];
+            }
+        }
+#else
         for (int e = tid; e < NB * FW * D; e += NTHREADS) {
             const int f = e / (FW * D), vd = e % (FW * D);
             const int n = n0 + f;
             wsl[vd * NBS + f] = (n < N) ? w[((long)n * FH + u) * FW * D + vd] : 0.f;
         }
+#endif
         __syncthreads();
 #endif
 

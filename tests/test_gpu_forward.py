@@ -122,6 +122,10 @@ DIRECT_CFGS = [
     "th=16 tw=16 p=4 q=8 nb=32 layout=1 fsrc=1",            # scalar weights, 4 filter groups
     "th=8 tw=32 p=4 q=16 nb=16 layout=0 fsrc=1 ud=2",       # scalar weights, one group
     "th=16 tw=32 p=8 q=4 nb=12 layout=1 fsrc=1",            # N not a multiple of nb: zero-padded copy
+    # staging loads issued in batches (input tile and filter slices)
+    "th=8 tw=16 p=2 q=8 nb=64 layout=1 ds=2 sb=1",
+    "th=16 tw=32 p=8 q=8 nb=64 layout=1 sb=1",
+    "th=8 tw=32 p=4 q=16 nb=16 layout=0 fsrc=1 ud=2 sb=1",
 ]
 
 
