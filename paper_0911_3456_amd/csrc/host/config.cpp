@@ -171,7 +171,7 @@ Config default_dw(const fbcorr_desc& d, int cus) {
     const int ho = d.H - d.fh + 1, wo = d.W - d.fw + 1;
     const long nchunks = (long)d.batch * cdiv(ho, 2) * cdiv(wo, 32);
     const int np = (int)std::max<long>(1, std::min<long>(nchunks, std::max(1, cus) / 2));
-    c.v = {{"rh", 2}, {"rw", 32}, {"nw", 8}, {"tpb", tpb}, {"np", np}, {"gpad", 4}, {"xpad", 4}, {"pf", 1},
+    c.v = {{"rh", 2}, {"rw", 32}, {"nw", 8}, {"tpb", tpb}, {"np", np}, {"gpad", 0}, {"xpad", 0}, {"pf", 1},
            {"bal", 0}, {"unr", 4}};
     return c;
 }

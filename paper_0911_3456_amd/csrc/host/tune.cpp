@@ -252,11 +252,15 @@ std::vector<Config> tune_candidates(const fbcorr_desc& d, int role, bool with_di
                         for (int np : nps)
                             for (int pf : {0, 1, 2})
                                 for (int bal : {0, 1})
-                                    for (int unr : {0, 4}) {
+                                    for (int unr : {0, 4})
+                                      for (int pad : {0, 4}) {
                                         Config c = base;
                                         c.v["rh"] = rh; c.v["rw"] = rw; c.v["nw"] = nw;
                                         c.v["tpb"] = (tiles + split - 1) / split;
                                         c.v["np"] = np; c.v["pf"] = pf; c.v["bal"] = bal; c.v["unr"] = unr;
+                                        // row padding of the staged dy and input tiles (0: each
+                                        // tile is one contiguous run in LDS)
+                                        c.v["gpad"] = pad; c.v["xpad"] = pad;
                                         // round-robin deals: empty last slots skipped
                                         c.v["skipe"] = bal ? 0 : 1;
                                         grid.push_back(c);

@@ -104,6 +104,8 @@ BW_CFGS = ["rh=2 rw=32 nw=4 tpb=21 np=64 pf=1", "rh=4 rw=16 nw=8 tpb=42 np=7 pf=
            # step loop unrolled completely, or by a factor that leaves a rest
            "rh=2 rw=30 nw=8 tpb=21 np=13 pf=1 unr=0", "rh=1 rw=62 nw=8 tpb=21 np=9 pf=2 bal=1 unr=0",
            "rh=2 rw=16 nw=4 tpb=14 np=20 pf=0 unr=3",
+           # padded rows of the staged tiles (the default keeps them contiguous)
+           "rh=2 rw=32 nw=8 tpb=21 np=64 pf=2 gpad=4 xpad=4", "rh=2 rw=61 nw=8 tpb=25 np=16 pf=2 bal=1 gpad=8 xpad=12",
            # waves with an empty last slot skip its products
            "rh=2 rw=30 nw=8 tpb=21 np=13 pf=1 unr=0 skipe=1", "rh=1 rw=32 nw=4 tpb=14 np=20 pf=2 skipe=1"]
 
